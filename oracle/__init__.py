@@ -1,0 +1,136 @@
+"""CPU oracle for the distance-map hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the HIP library: the C file
+``edt_ref.c`` is built here with gcc into ``liboracle.so``, and ``brute``
+holds an independent all-pairs reference used to pin it.
+
+Functions (each cites the paper passage it follows in its docstring):
+  edt(occ)              exact squared EDT + nearest-site index (Sec. III-C)
+  insert_points(...)    point-cloud insertion (Sec. III-A)
+  insert_links(...)     link voxel models placed by joint state (Sec. III-A)
+  query_spheres(...)    closest obstacle at sphere centres (Alg. 2, Eq. dist)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "edt_ref.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+QUERY_WORDS = 16     # 4-byte words per sphere result
+Q_OUT_OF_MAP = 1
+Q_EMPTY = 2
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (-O2, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_edt.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int]
+        lib.oracle_edt.restype = ctypes.c_int
+        lib.oracle_insert_points.argtypes = [ctypes.c_int] * 3 + [P, ctypes.c_float, P, P,
+                                                                   ctypes.c_int64, P, P]
+        lib.oracle_insert_points.restype = None
+        lib.oracle_insert_links.argtypes = [ctypes.c_int] * 3 + [P, ctypes.c_float, P, P, P,
+                                                                  ctypes.c_int, P, ctypes.c_uint64]
+        lib.oracle_insert_links.restype = None
+        lib.oracle_query_spheres.argtypes = [ctypes.c_int] * 3 + [P, ctypes.c_float, P, P, P, P,
+                                                                   ctypes.c_int, P]
+        lib.oracle_query_spheres.restype = None
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def edt(occ: np.ndarray, nthreads: int = 0):
+    """Exact squared EDT of an occupancy grid [nz, ny, nx] (Sec. III-C, Alg. 1).
+
+    Returns (d2 int32, site int32) of the same shape; site is the linear index
+    x + nx*(y + ny*z) of the nearest occupied voxel, the smallest such index
+    on ties; an empty grid gives INT32_MAX / -1 everywhere.
+    """
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    nz, ny, nx = occ.shape
+    d2 = np.empty(occ.shape, np.int32)
+    site = np.empty(occ.shape, np.int32)
+    rc = _load().oracle_edt(_ptr(occ), nx, ny, nz, _ptr(d2), _ptr(site), int(nthreads))
+    if rc != 0:
+        raise RuntimeError("oracle_edt failed")
+    return d2, site
+
+
+def _grid_args(grid):
+    origin = np.asarray(grid.origin, np.float32)
+    return grid.nx, grid.ny, grid.nz, origin, np.float32(grid.voxel)
+
+
+def insert_points(grid, occ: np.ndarray, pts: np.ndarray, T: np.ndarray,
+                  exclude: np.ndarray | None = None) -> np.ndarray:
+    """OR a point cloud into occ (Sec. III-A); returns occ (modified in place)."""
+    nx, ny, nz, origin, v = _grid_args(grid)
+    pts = np.ascontiguousarray(pts, np.float32).reshape(-1, 3)
+    T = np.ascontiguousarray(T, np.float32).reshape(12)
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous and occ.size == grid.n
+    ex = None if exclude is None else np.ascontiguousarray(exclude, np.uint8)
+    _load().oracle_insert_points(nx, ny, nz, _ptr(origin), v, _ptr(occ), _ptr(pts),
+                                 pts.shape[0], _ptr(T), None if ex is None else _ptr(ex))
+    return occ
+
+
+def insert_links(grid, occ: np.ndarray, link_pts: np.ndarray, link_off: np.ndarray,
+                 poses: np.ndarray, mask: int) -> np.ndarray:
+    """OR the masked links' voxel models, placed by their poses (Sec. III-A)."""
+    nx, ny, nz, origin, v = _grid_args(grid)
+    lp = np.ascontiguousarray(link_pts, np.float32).reshape(-1, 3)
+    lo = np.ascontiguousarray(link_off, np.int32)
+    ps = np.ascontiguousarray(poses, np.float32).reshape(-1, 12)
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous and occ.size == grid.n
+    _load().oracle_insert_links(nx, ny, nz, _ptr(origin), v, _ptr(occ), _ptr(lp), _ptr(lo),
+                                lo.size - 1, _ptr(ps), ctypes.c_uint64(mask))
+    return occ
+
+
+def query_spheres(grid, d2: np.ndarray, site: np.ndarray, centres: np.ndarray,
+                  radii: np.ndarray) -> np.ndarray:
+    """Closest-obstacle query at sphere centres (Alg. 2; Eq. dist).
+
+    Returns uint32 [m, 16]: d2, site, voxel[3], flags, dist_vox, x_c,
+    clearance, grad[3], nearest[3], 0 (floats as raw bits).
+    """
+    nx, ny, nz, origin, v = _grid_args(grid)
+    c = np.ascontiguousarray(centres, np.float32).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, np.float32).reshape(-1)
+    d2 = np.ascontiguousarray(d2, np.int32)
+    site = np.ascontiguousarray(site, np.int32)
+    out = np.zeros((c.shape[0], QUERY_WORDS), np.uint32)
+    _load().oracle_query_spheres(nx, ny, nz, _ptr(origin), v, _ptr(d2), _ptr(site), _ptr(c),
+                                 _ptr(r), c.shape[0], _ptr(out))
+    return out

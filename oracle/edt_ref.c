@@ -1,0 +1,336 @@
+/*
+ * CPU oracle for the distance-map hot path.  TEST INFRASTRUCTURE ONLY: the
+ * tests, the smoke check and the benchmark's CPU-baseline leg call it; the
+ * product library never does, and it shares no code, header or table with
+ * the HIP path.
+ *
+ * Plain, slow and written to be checked by eye against the paper:
+ *
+ *   oracle_edt            exact squared EDT + nearest-site index, following
+ *                         the four steps of the parallel banding algorithm
+ *                         (Sec. III-C, Alg. 1) with one band per line:
+ *                         step 1 nearest site in each row, step 2 proximate
+ *                         sites of each column by a stack with a dominance
+ *                         test, step 3 nearest-site query walking that stack,
+ *                         step 4 steps 2-3 again along z.  All arithmetic is
+ *                         int64.
+ *   oracle_insert_points  point-cloud insertion (Sec. III-A): transform to
+ *                         the map frame, discretize, set occupancy, skip
+ *                         voxels the robot map occupies.
+ *   oracle_insert_links   link voxel models placed by joint state (Sec. III-A,
+ *                         Alg. 2 UpdateLinks/Insert).
+ *   oracle_query_spheres  closest-obstacle extraction at sphere centres
+ *                         (Alg. 2 ExtractClosestObstaclePose; Eq. dist).
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *   - tie rule: every step keeps the smaller coordinate on equal distance;
+ *     with the passes in x, y, z order the final site is the smallest linear
+ *     index among the equidistant occupied voxels;
+ *   - empty map: d2 = INT32_MAX, site = -1; no sites outside the grid;
+ *   - any nonzero occupancy byte is occupied;
+ *   - float op order of insert / query is fixed (fmaf chain, correctly
+ *     rounded divide and sqrt, floorf) so a device implementation can match
+ *     bit for bit.  Build with -ffp-contract=off.
+ *
+ * Parity pins (tests/test_oracle_*.py): brute force over all sites on small
+ * grids, closed forms for single sites and 1D rows, invariants (zero exactly
+ * on occupied voxels, 1-Lipschitz, local optimality, sums of three squares).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NONE (-1)
+
+/* ------------------------------------------------------------------------ */
+/* Step 1: nearest occupied voxel within a row (one "band" per row).        */
+/* For each x, the nearest x' with occ != 0; on a tie the smaller x'.       */
+/* ------------------------------------------------------------------------ */
+static void row_nearest(const uint8_t* row, int n, int32_t* xs)
+{
+    /* left-to-right sweep: last site at or before x */
+    int last = NONE;
+    for (int x = 0; x < n; ++x) {
+        if (row[x]) last = x;
+        xs[x] = last;
+    }
+    /* right-to-left sweep: next site at or after x; keep the closer,
+     * the left one on a tie */
+    int next = NONE;
+    for (int x = n - 1; x >= 0; --x) {
+        if (row[x]) next = x;
+        if (next != NONE) {
+            if (xs[x] == NONE || (int64_t)(next - x) < (int64_t)(x - xs[x]))
+                xs[x] = next;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Steps 2 and 3 along one line of length n.                                */
+/* Input: for each position p, g[p] = squared distance already accumulated */
+/* in the other axes to that position's site, or -1 if it has no site.      */
+/* Output: for each position q, the chosen site position best[q] (or NONE)  */
+/* and the total squared distance dist[q] = g[best] + (q - best)^2.          */
+/* ------------------------------------------------------------------------ */
+
+/* value of site a's distance function at position q */
+static int64_t f_at(int64_t a, int64_t ga, int64_t q)
+{
+    return ga + (q - a) * (q - a);
+}
+
+/* Is the site b (between a and c) dominated, i.e. is the stretch of the
+ * line where b beats both a and c empty?  The boundary between a and b is
+ * where f_a = f_b: q_ab = ((g_b+b^2) - (g_a+a^2)) / (2(b-a)).  b has no
+ * stretch of its own iff q_bc <= q_ab; cross-multiplying by the positive
+ * denominators keeps it exact. */
+static int dominated(int64_t a, int64_t ga, int64_t b, int64_t gb, int64_t c, int64_t gc)
+{
+    int64_t ka = ga + a * a, kb = gb + b * b, kc = gc + c * c;
+    return (kc - kb) * (b - a) <= (kb - ka) * (c - b);
+}
+
+static void line_envelope(const int64_t* g, int n, int32_t* best, int64_t* dist,
+                          int32_t* stack /* scratch, n entries */)
+{
+    /* step 2: ComputeProximateSite -- sweep sites in order with a stack */
+    int top = 0;
+    for (int c = 0; c < n; ++c) {
+        if (g[c] < 0) continue;
+        while (top >= 2) {
+            int a = stack[top - 2], b = stack[top - 1];
+            if (dominated(a, g[a], b, g[b], c, g[c])) --top;
+            else break;
+        }
+        stack[top++] = c;
+    }
+    /* step 3: QueryNearestSite -- for each position walk the stack while
+     * the next proximate site is strictly closer (ties keep the smaller) */
+    int k = 0;
+    for (int q = 0; q < n; ++q) {
+        if (top == 0) { best[q] = NONE; dist[q] = -1; continue; }
+        while (k + 1 < top && f_at(stack[k + 1], g[stack[k + 1]], q) < f_at(stack[k], g[stack[k]], q))
+            ++k;
+        best[q] = stack[k];
+        dist[q] = f_at(stack[k], g[stack[k]], q);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full 3D transform.  occ is [nz][ny][nx] with x fastest.                  */
+/* d2 and site receive nx*ny*nz int32 values.  Returns 0, or -1 on bad args. */
+/* nthreads <= 0 uses the OpenMP default; lines within a step are           */
+/* independent, so the thread count does not change any value.             */
+/* ------------------------------------------------------------------------ */
+int oracle_edt(const uint8_t* occ, int nx, int ny, int nz, int32_t* d2,
+               int32_t* site, int nthreads)
+{
+    if (!occ || !d2 || !site || nx < 1 || ny < 1 || nz < 1) return -1;
+    const int64_t N = (int64_t)nx * ny * nz;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    /* step 1 result: x' of the nearest site in the row (sx1); steps 2-3
+     * result: the 2D site (sx2, sy2) of each voxel within its slice */
+    int32_t* sx1 = (int32_t*)malloc(sizeof(int32_t) * N);
+    int32_t* sx2 = (int32_t*)malloc(sizeof(int32_t) * N);
+    int32_t* sy2 = (int32_t*)malloc(sizeof(int32_t) * N);
+    if (!sx1 || !sx2 || !sy2) { free(sx1); free(sx2); free(sy2); return -1; }
+
+    /* step 1, every row of every slice */
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < (int64_t)ny * nz; ++r)
+        row_nearest(occ + r * nx, nx, sx1 + r * nx);
+
+    /* steps 2-3 along y, for each column x of each slice z */
+#pragma omp parallel
+    {
+        int64_t* g = (int64_t*)malloc(sizeof(int64_t) * ny);
+        int64_t* dist = (int64_t*)malloc(sizeof(int64_t) * ny);
+        int32_t* best = (int32_t*)malloc(sizeof(int32_t) * ny);
+        int32_t* stk = (int32_t*)malloc(sizeof(int32_t) * ny);
+#pragma omp for schedule(static)
+        for (int64_t col = 0; col < (int64_t)nx * nz; ++col) {
+            int64_t z = col / nx, x = col % nx;
+            for (int y = 0; y < ny; ++y) {
+                int32_t xp = sx1[x + (int64_t)nx * (y + (int64_t)ny * z)];
+                g[y] = (xp == NONE) ? -1 : (x - xp) * (x - xp);
+            }
+            line_envelope(g, ny, best, dist, stk);
+            for (int y = 0; y < ny; ++y) {
+                int64_t i = x + (int64_t)nx * (y + (int64_t)ny * z);
+                if (best[y] == NONE) { sx2[i] = NONE; sy2[i] = NONE; continue; }
+                sx2[i] = sx1[x + (int64_t)nx * (best[y] + (int64_t)ny * z)];
+                sy2[i] = best[y];
+            }
+        }
+        free(g); free(dist); free(best); free(stk);
+    }
+
+    /* step 4: steps 2-3 along z for each (x, y) column, over the 2D sites */
+#pragma omp parallel
+    {
+        int64_t* g = (int64_t*)malloc(sizeof(int64_t) * nz);
+        int64_t* dist = (int64_t*)malloc(sizeof(int64_t) * nz);
+        int32_t* best = (int32_t*)malloc(sizeof(int32_t) * nz);
+        int32_t* stk = (int32_t*)malloc(sizeof(int32_t) * nz);
+#pragma omp for schedule(static)
+        for (int64_t col = 0; col < (int64_t)nx * ny; ++col) {
+            int64_t y = col / nx, x = col % nx;
+            for (int z = 0; z < nz; ++z) {
+                int64_t i = x + (int64_t)nx * (y + (int64_t)ny * z);
+                if (sx2[i] == NONE) g[z] = -1;
+                else g[z] = (x - sx2[i]) * (x - sx2[i]) + (y - sy2[i]) * (y - sy2[i]);
+            }
+            line_envelope(g, nz, best, dist, stk);
+            for (int z = 0; z < nz; ++z) {
+                int64_t i = x + (int64_t)nx * (y + (int64_t)ny * z);
+                if (best[z] == NONE) { d2[i] = INT32_MAX; site[i] = NONE; continue; }
+                int64_t j = x + (int64_t)nx * (y + (int64_t)ny * best[z]);
+                d2[i] = (int32_t)dist[z];
+                site[i] = (int32_t)(sx2[j] + (int64_t)nx * (sy2[j] + (int64_t)ny * best[z]));
+            }
+        }
+        free(g); free(dist); free(best); free(stk);
+    }
+    free(sx1); free(sx2); free(sy2);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Insertion (Sec. III-A).  T is a row-major 3x4 [R | t].                  */
+/* ------------------------------------------------------------------------ */
+
+/* map-frame coordinate: fixed fmaf chain R0*px + R1*py + R2*pz + t */
+static float xform_row(const float* T, int r, float px, float py, float pz)
+{
+    return fmaf(T[4 * r + 2], pz, fmaf(T[4 * r + 1], py, fmaf(T[4 * r + 0], px, T[4 * r + 3])));
+}
+
+/* voxel coordinate u = (x - origin) / voxel; kept iff 0 <= u < n */
+static int discretize(float x, float o, float v, int n, int* out)
+{
+    float u = (x - o) / v;
+    if (!(u >= 0.0f && u < (float)n)) return 0;  /* also drops NaN */
+    *out = (int)floorf(u);
+    return 1;
+}
+
+static void insert_one(const float* T, const float* p, int nx, int ny, int nz,
+                       const float* origin, float voxel, uint8_t* occ, const uint8_t* exclude)
+{
+    float x = xform_row(T, 0, p[0], p[1], p[2]);
+    float y = xform_row(T, 1, p[0], p[1], p[2]);
+    float z = xform_row(T, 2, p[0], p[1], p[2]);
+    int ix, iy, iz;
+    if (!discretize(x, origin[0], voxel, nx, &ix)) return;
+    if (!discretize(y, origin[1], voxel, ny, &iy)) return;
+    if (!discretize(z, origin[2], voxel, nz, &iz)) return;
+    int64_t lin = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
+    if (exclude && exclude[lin]) return;   /* robot-part filtering */
+    occ[lin] = 1;
+}
+
+void oracle_insert_points(int nx, int ny, int nz, const float* origin, float voxel,
+                          uint8_t* occ, const float* pts, int64_t n, const float* T,
+                          const uint8_t* exclude)
+{
+    for (int64_t i = 0; i < n; ++i)
+        insert_one(T, pts + 3 * i, nx, ny, nz, origin, voxel, occ, exclude);
+}
+
+void oracle_insert_links(int nx, int ny, int nz, const float* origin, float voxel,
+                         uint8_t* occ, const float* link_pts, const int32_t* link_off,
+                         int n_links, const float* poses, uint64_t mask)
+{
+    for (int l = 0; l < n_links; ++l) {
+        if (!((mask >> l) & 1u)) continue;
+        for (int32_t i = link_off[l]; i < link_off[l + 1]; ++i)
+            insert_one(poses + 12 * l, link_pts + 3 * (int64_t)i, nx, ny, nz, origin,
+                       voxel, occ, NULL);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sphere query (Alg. 2 ExtractClosestObstaclePose; Eq. dist).              */
+/* Each result is 16 x 4-byte words:                                        */
+/*  0 d2  1 site  2..4 voxel  5 flags  6 dist_vox  7 x_c  8 clearance       */
+/*  9..11 gradient  12..14 nearest obstacle centre O  15 zero               */
+/* flags: 1 = centre outside the map, 2 = map empty.                        */
+/* ------------------------------------------------------------------------ */
+static float dist_at(const int32_t* d2, int64_t lin) { return sqrtf((float)d2[lin]); }
+
+void oracle_query_spheres(int nx, int ny, int nz, const float* origin, float voxel,
+                          const int32_t* d2, const int32_t* site, const float* centres,
+                          const float* radii, int m, uint32_t* out)
+{
+    const int n3[3] = {nx, ny, nz};
+    for (int i = 0; i < m; ++i) {
+        uint32_t* o = out + 16 * (int64_t)i;
+        union { float f; uint32_t u; int32_t s; } w[16];
+        memset(w, 0, sizeof(w));
+        const float* c = centres + 3 * i;
+        float r = radii[i];
+        int v[3], inside = 1;
+        for (int a = 0; a < 3; ++a)
+            if (!discretize(c[a], origin[a], voxel, n3[a], &v[a])) inside = 0;
+        if (!inside) {
+            /* outside the map: conservative distance 0, obstacle at centre */
+            w[0].s = 0; w[1].s = NONE;
+            w[2].s = w[3].s = w[4].s = -1;
+            w[5].s = 1;
+            w[6].f = 0.0f; w[7].f = 0.0f; w[8].f = -r;
+            w[12].f = c[0]; w[13].f = c[1]; w[14].f = c[2];
+        } else {
+            int64_t lin = v[0] + (int64_t)nx * (v[1] + (int64_t)ny * v[2]);
+            w[0].s = d2[lin]; w[1].s = site[lin];
+            w[2].s = v[0]; w[3].s = v[1]; w[4].s = v[2];
+            if (site[lin] == NONE) {
+                w[5].s = 2;
+                w[6].f = INFINITY; w[7].f = INFINITY; w[8].f = INFINITY;
+                w[12].f = INFINITY; w[13].f = INFINITY; w[14].f = INFINITY;
+            } else {
+                int32_t s = site[lin];
+                int sxyz[3] = {s % nx, (s / nx) % ny, s / (nx * ny)};
+                float O[3], dd[3];
+                for (int a = 0; a < 3; ++a) {
+                    O[a] = fmaf((float)sxyz[a] + 0.5f, voxel, origin[a]);
+                    dd[a] = O[a] - c[a];
+                }
+                float xc = sqrtf(fmaf(dd[2], dd[2], fmaf(dd[1], dd[1], dd[0] * dd[0])));
+                w[6].f = dist_at(d2, lin);
+                w[7].f = xc;
+                w[8].f = xc - r;
+                /* central difference of sqrt(d2) over +-1 voxel, one-sided
+                 * at the borders, zero along an axis of length 1 */
+                const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
+                for (int a = 0; a < 3; ++a) {
+                    float g;
+                    if (n3[a] == 1) g = 0.0f;
+                    else if (v[a] == 0) g = dist_at(d2, lin + stride[a]) - dist_at(d2, lin);
+                    else if (v[a] == n3[a] - 1) g = dist_at(d2, lin) - dist_at(d2, lin - stride[a]);
+                    else g = 0.5f * (dist_at(d2, lin + stride[a]) - dist_at(d2, lin - stride[a]));
+                    w[9 + a].f = g;
+                }
+                w[12].f = O[0]; w[13].f = O[1]; w[14].f = O[2];
+            }
+        }
+        for (int k = 0; k < 16; ++k) o[k] = w[k].u;
+    }
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,215 @@
+"""Pins of the CPU oracle's insertion and sphere query.
+
+Insertion (Sec. III-A): a point maps to the voxel containing its map-frame
+position.  Pins: voxel centres under the identity land in their own voxel;
+under random rigid transforms the float32 result agrees with the exact
+(float64) voxel wherever the point is not within rounding distance of a
+voxel face; NaN and off-map points are dropped; robot voxels are excluded;
+order and repetition do not matter; a half-voxel lattice covers every voxel
+whose inscribed ball lies in the link capsule.
+
+Query (Alg. 2 ExtractClosestObstaclePose, Eq. dist): on a single-site map
+every field has a closed form.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2407_02363_amd import inputs
+
+G = inputs.Grid(20, 24, 16, (0.1, -0.2, 0.05), 0.02)
+
+
+def test_identity_voxel_centres(oracle_lib):
+    occ = np.zeros(G.shape, np.uint8)
+    g = inputs.rng(0)
+    idx = np.stack([g.integers(0, G.nx, 500), g.integers(0, G.ny, 500), g.integers(0, G.nz, 500)], -1)
+    pts = (idx + 0.5) * G.voxel + np.array(G.origin)
+    T = inputs.pose12(np.eye(3), np.zeros(3))
+    oracle_lib.insert_points(G, occ, pts.astype(np.float32), T)
+    expect = np.zeros(G.shape, np.uint8)
+    expect[idx[:, 2], idx[:, 1], idx[:, 0]] = 1
+    assert np.array_equal(occ, expect)
+
+
+def test_rigid_transform_matches_exact_away_from_faces(oracle_lib):
+    g = inputs.rng(1)
+    for trial in range(5):
+        R = inputs.rot_z(g.uniform(0, 6.3)) @ inputs.rot_y(g.uniform(0, 6.3)) @ inputs.rot_x(g.uniform(0, 6.3))
+        t = g.uniform(-0.2, 0.6, size=3)
+        T = inputs.pose12(R, t)
+        Tm = T.astype(np.float64).reshape(3, 4)
+        pts = g.uniform(-0.6, 0.8, size=(4000, 3)).astype(np.float32)
+        xm = pts.astype(np.float64) @ Tm[:, :3].T + Tm[:, 3]
+        u = (xm - np.array(G.origin)) / G.voxel
+        n = np.array([G.nx, G.ny, G.nz])
+        frac = np.abs(u - np.rint(u))
+        safe = (frac > 1e-3).all(1)
+        inside = ((u >= 0) & (u < n)).all(1) & safe
+        occ = np.zeros(G.shape, np.uint8)
+        oracle_lib.insert_points(G, occ, pts[safe], T)
+        vi = np.floor(u[inside]).astype(int)
+        expect = np.zeros(G.shape, np.uint8)
+        expect[vi[:, 2], vi[:, 1], vi[:, 0]] = 1
+        assert np.array_equal(occ, expect), trial
+
+
+def test_faces_nan_offmap_exclude(oracle_lib):
+    T = inputs.pose12(np.eye(3), np.zeros(3))
+    G1 = inputs.Grid(4, 4, 4, (0.0, 0.0, 0.0), 0.25)
+    pts = np.array([[0.0, 0.0, 0.0],        # corner of voxel 0 -> voxel 0
+                    [0.25, 0.5, 0.75],      # exact faces -> voxel (1,2,3)
+                    [1.0, 0.1, 0.1],        # u == n -> dropped
+                    [-1e-7, 0.1, 0.1],      # just below 0 -> dropped
+                    [np.nan, 0.1, 0.1],     # NaN -> dropped
+                    [0.1, np.inf, 0.1],     # inf -> dropped
+                    [-0.0, 0.1, 0.1]],      # -0 -> voxel (0,0,0)
+                   np.float32)
+    occ = np.zeros(G1.shape, np.uint8)
+    oracle_lib.insert_points(G1, occ, pts, T)
+    assert occ.sum() == 2 and occ[0, 0, 0] == 1 and occ[3, 2, 1] == 1
+    ex = np.zeros(G1.shape, np.uint8)
+    ex[3, 2, 1] = 1
+    occ2 = np.zeros(G1.shape, np.uint8)
+    oracle_lib.insert_points(G1, occ2, pts, T, exclude=ex)
+    assert occ2.sum() == 1 and occ2[0, 0, 0] == 1
+
+
+def test_order_and_reinsertion_invariance(oracle_lib):
+    ci = inputs.cycle_inputs(0, n_frames=1)
+    g = ci.grid
+    pts = ci.frames[0]
+    a = np.zeros(g.shape, np.uint8)
+    oracle_lib.insert_points(g, a, pts, ci.T_map_cam)
+    perm = inputs.rng(3).permutation(pts.shape[0])
+    b = np.zeros(g.shape, np.uint8)
+    oracle_lib.insert_points(g, b, pts[perm], ci.T_map_cam)
+    oracle_lib.insert_points(g, b, pts, ci.T_map_cam)
+    assert np.array_equal(a, b) and a.sum() > 10000
+    d2a, sa = oracle_lib.edt(a)
+    d2b, sb = oracle_lib.edt(b)
+    assert np.array_equal(d2a, d2b) and np.array_equal(sa, sb)
+
+
+def _seg_dist(p, a, b):
+    ab = b - a
+    t = np.clip(((p - a) @ ab) / (ab @ ab), 0, 1)
+    return np.linalg.norm(p - (a + t[:, None] * ab), axis=1)
+
+
+def test_link_lattice_covers_capsule_and_mask(oracle_lib):
+    G2 = inputs.Grid(64, 64, 64, (0.0, 0.0, 0.0), 0.01)
+    robot = inputs.make_robot(5, base=(0.32, 0.32, 0.1), l_lo=0.08, l_hi=0.12, r_lo=0.03, r_hi=0.05)
+    lp, lo = inputs.link_models(robot, G2.voxel)
+    q = inputs.random_joint_states(1, 9)[0]
+    poses = robot.poses12(q)
+    F = robot.fk(q)
+    for l in range(robot.n_links):
+        occ = np.zeros(G2.shape, np.uint8)
+        oracle_lib.insert_links(G2, occ, lp, lo, poses, 1 << l)
+        z, y, x = np.meshgrid(np.arange(64), np.arange(64), np.arange(64), indexing="ij")
+        c = (np.stack([x.ravel(), y.ravel(), z.ravel()], -1) + 0.5) * G2.voxel
+        a = F[l, :, 3]
+        b = a + F[l, :, 2] * robot.lengths[l]
+        d = _seg_dist(c, a, b).reshape(G2.shape)
+        # every voxel whose inscribed ball is well inside the capsule is hit
+        must = d <= robot.radii[l] - math.sqrt(3) / 4 * G2.voxel - 1e-6
+        assert occ[must].all(), l
+        # nothing lands farther than half a voxel diagonal outside it
+        assert (d[occ != 0] <= robot.radii[l] + math.sqrt(3) / 2 * G2.voxel + 1e-6).all(), l
+    # the mask selects links: all-links equals the union of single links
+    occ_all = np.zeros(G2.shape, np.uint8)
+    oracle_lib.insert_links(G2, occ_all, lp, lo, poses, 0xFF)
+    union = np.zeros(G2.shape, np.uint8)
+    for l in range(8):
+        oracle_lib.insert_links(G2, union, lp, lo, poses, 1 << l)
+    assert np.array_equal(occ_all, union)
+    none = np.zeros(G2.shape, np.uint8)
+    oracle_lib.insert_links(G2, none, lp, lo, poses, 0)
+    assert none.sum() == 0
+
+
+def test_query_single_site_closed_form(oracle_lib):
+    G3 = inputs.Grid(40, 30, 20, (-0.3, 0.2, 0.0), 0.05)
+    s = (17, 11, 6)
+    occ = inputs.single_site_grid(G3.shape, s)
+    d2, site = oracle_lib.edt(occ)
+    g = inputs.rng(4)
+    m = 300
+    C = (np.array(G3.origin) + g.uniform(0, 1, (m, 3)) * np.array(G3.extent)).astype(np.float32)
+    r = g.uniform(0.01, 0.2, m).astype(np.float32)
+    out = oracle_lib.query_spheres(G3, d2, site, C, r)
+    ints = out.view(np.int32)
+    fl = out.view(np.float32)
+    v = np.floor((C.astype(np.float64) - np.array(G3.origin)) / G3.voxel).astype(int)
+    assert (ints[:, 5] == 0).all()
+    assert np.array_equal(ints[:, 2:5], v)
+    dd = ((v - np.array(s)) ** 2).sum(1)
+    assert np.array_equal(ints[:, 0], dd)
+    assert (ints[:, 1] == s[0] + 40 * (s[1] + 30 * s[2])).all()
+    assert np.array_equal(fl[:, 6], np.sqrt(dd.astype(np.float32)))
+    O = (np.array(s) + 0.5) * G3.voxel + np.array(G3.origin)
+    assert np.allclose(fl[:, 12:15], O, atol=1e-6)
+    xc = np.linalg.norm(O - C.astype(np.float64), axis=1)
+    assert np.allclose(fl[:, 7], xc, rtol=1e-6, atol=1e-7)
+    assert np.allclose(fl[:, 8], xc - r, rtol=1e-5, atol=1e-6)
+    # gradient of the distance field: unit vector away from the site, up to
+    # the central difference's truncation error, away from the site/borders
+    far = (np.sqrt(dd) >= 6) & (v > 0).all(1) & (v < np.array([39, 29, 19])).all(1)
+    gexp = (v - np.array(s)) / np.sqrt(np.maximum(dd, 1))[:, None]
+    assert far.sum() > 50
+    assert np.abs(fl[far, 9:12] - gexp[far]).max() < 0.05
+
+
+def test_query_borders_flags(oracle_lib):
+    G4 = inputs.Grid(8, 1, 5, (0.0, 0.0, 0.0), 0.1)
+    occ = np.zeros(G4.shape, np.uint8)
+    occ[2, 0, 3] = 1
+    d2, site = oracle_lib.edt(occ)
+    C = np.array([[0.05, 0.05, 0.05],       # voxel (0,0,0): one-sided x and z
+                  [0.75, 0.05, 0.45],       # voxel (7,0,4): one-sided the other way
+                  [0.85, 0.05, 0.05],       # outside (x)
+                  [np.nan, 0.0, 0.0]], np.float32)
+    r = np.full(4, 0.1, np.float32)
+    out = oracle_lib.query_spheres(G4, d2, site, C, r)
+    ints, fl = out.view(np.int32), out.view(np.float32)
+    D = np.sqrt(d2.astype(np.float32))
+    assert fl[0, 9] == D[0, 0, 1] - D[0, 0, 0]
+    assert fl[0, 11] == D[1, 0, 0] - D[0, 0, 0]
+    assert fl[0, 10] == 0.0            # axis of length 1
+    assert fl[1, 9] == D[4, 0, 7] - D[4, 0, 6]
+    assert fl[1, 11] == D[4, 0, 7] - D[3, 0, 7]
+    for i in (2, 3):
+        assert ints[i, 5] == 1 and ints[i, 0] == 0 and ints[i, 1] == -1
+        assert fl[i, 8] == np.float32(-0.1)
+    # empty map
+    empty = np.zeros(G4.shape, np.uint8)
+    e2, es = oracle_lib.edt(empty)
+    out = oracle_lib.query_spheres(G4, e2, es, C[:1], r[:1])
+    assert out.view(np.int32)[0, 5] == 2 and np.isinf(out.view(np.float32)[0, 7])
+
+
+def test_sphere_rule_closed_form():
+    """OBB-aligned spheres (Sec. III-B): diameter sqrt(d1^2+d2^2), count
+    ceil(d3/diameter + 1), centres evenly spaced from end to end of the box.
+
+    What the rule guarantees: consecutive centres are at most one diameter
+    apart (k - 1 >= d3/diameter), so the spheres overlap along the whole long
+    axis, and each sphere contains the box's cross-section in its own centre
+    plane (the face diagonal is the diameter).  It does not contain the whole
+    box, so the paper's "inscription" is read in that weaker sense."""
+    for r, l in [(0.04, 0.2), (0.08, 0.4), (0.06, 0.3), (0.03, 0.07)]:
+        c, rad = inputs.bounding_spheres_link(r, l)
+        d3 = l + 2 * r
+        dia = math.sqrt(8) * r
+        k = len(rad)
+        assert k == math.ceil(d3 / dia + 1)
+        assert np.allclose(rad, dia / 2)
+        assert np.allclose(c[:, :2], 0) and np.isclose(c[0, 2], -r) and np.isclose(c[-1, 2], l + r)
+        gaps = np.diff(c[:, 2])
+        assert np.allclose(gaps, d3 / (k - 1)) and (gaps <= dia + 1e-12).all()
+        corners = np.array([[sx * r, sy * r] for sx in (-1, 1) for sy in (-1, 1)])
+        assert np.allclose(np.linalg.norm(corners, axis=1), dia / 2)
+        axis = np.linspace(-r, l + r, 1001)
+        assert (np.min(np.abs(axis[:, None] - c[None, :, 2]), axis=1) <= dia / 2 + 1e-12).all()
