@@ -1,0 +1,164 @@
+/*
+ * edt.h -- C ABI of libedtmi.so: exact GPU distance maps for real-time
+ * collision avoidance (Bedada & Palli, "Real Time Collision Avoidance with
+ * GPU-Computed Distance Maps", arXiv 2407.02363) on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * One control cycle (Alg. 2): clear the maps, insert the robot's link voxel
+ * models by joint state and the point cloud, compute the exact Euclidean
+ * distance transform (Sec. III-C, Alg. 1), and extract the closest obstacle
+ * at each bounding-sphere centre (ExtractClosestObstaclePose; Eq. dist).
+ *
+ * Conventions shared by every call:
+ *   - Grid layout: a map is a dense array indexed lin = x + nx*(y + ny*z)
+ *     (x fastest); 1 <= nx, ny, nz <= 1024.  origin is the map-frame position
+ *     (metres) of the MIN corner of voxel (0,0,0); voxel is the edge length.
+ *   - Pointers are DEVICE pointers unless stated otherwise.  The caller owns
+ *     every buffer; no call allocates or frees device memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *     call only enqueues work on it and returns without synchronising, so
+ *     the calls can be captured into a HIP graph.
+ *   - Return value: EDT_OK (0) or a negative status.  Argument and shape
+ *     errors are detected before anything is enqueued; nothing is launched
+ *     then.  A failed launch returns EDT_ERR_HIP.  edt_last_error() gives a
+ *     message for the last failure on the calling thread.  Faults inside a
+ *     kernel surface at the caller's next synchronisation of the stream.
+ */
+#ifndef EDTMI_EDT_H
+#define EDTMI_EDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct edt_grid_t {
+    int32_t nx, ny, nz;   /* voxels per axis, 1..1024 each */
+    float origin[3];      /* metres, min corner of voxel (0,0,0) */
+    float voxel;          /* edge length in metres, finite and > 0 */
+} edt_grid_t;
+
+/* One sphere query result (64 bytes). */
+typedef struct edt_sphere_result_t {
+    int32_t d2;           /* squared distance (voxels^2) at the centre's voxel */
+    int32_t site;         /* linear index of the nearest occupied voxel */
+    int32_t vox[3];       /* voxel containing the centre */
+    int32_t flags;        /* EDT_Q_OUT_OF_MAP | EDT_Q_EMPTY, 0 if neither */
+    float dist_vox;       /* sqrt(d2), voxels */
+    float x_c;            /* ||O - C||, metres: Eq. dist with O the centre of
+                             the nearest occupied voxel */
+    float clearance;      /* x_c - radius, metres */
+    float grad[3];        /* central difference of sqrt(d2) over +-1 voxel
+                             (one-sided at the map border, 0 along an axis of
+                             length 1), voxels per voxel */
+    float nearest[3];     /* O, metres, map frame */
+    float reserved;       /* 0 */
+} edt_sphere_result_t;
+
+enum {
+    EDT_OK = 0,
+    EDT_ERR_ARG = -1,         /* null pointer, negative count, bad flag */
+    EDT_ERR_SHAPE = -2,       /* grid dimensions or voxel size out of range */
+    EDT_ERR_WORKSPACE = -3,   /* workspace missing or too small */
+    EDT_ERR_HIP = -4,         /* a HIP runtime call failed */
+    EDT_ERR_UNSUPPORTED = -5  /* valid request this build does not handle */
+};
+
+enum { EDT_Q_OUT_OF_MAP = 1, EDT_Q_EMPTY = 2 };
+
+/* Message for a status code (static string). */
+const char* edt_status_string(int status);
+/* Message of the last failed call on this thread ("" if none). */
+const char* edt_last_error(void);
+/* Library version string. */
+const char* edt_version(void);
+
+/*
+ * edt_clear -- ClearMap of Alg. 2: set all nx*ny*nz bytes of occ to 0.
+ * Uses a fill kernel (not a memset node), so it is safe to capture.
+ */
+int edt_clear(const edt_grid_t* grid, uint8_t* occ, void* stream);
+
+/*
+ * edt_insert_points -- insert a point cloud into an occupancy map
+ * (Sec. III-A; Alg. 2 Insert(Point_Cloud)).
+ *   pts       float32 [n][3], sensor frame.  NaN/inf or off-map points are
+ *             dropped silently.
+ *   n         number of points, >= 0 (0 enqueues nothing).
+ *   T_map_sensor  float32 [12], device, row-major 3x4 [R | t] taking sensor
+ *             coordinates to map coordinates.
+ *   exclude   nullable uint8 [nx*ny*nz]: a point whose voxel is nonzero here
+ *             (the robot's own map) is not inserted (robot-part filtering).
+ * For each point, with fixed float32 op order:
+ *   m_r = fmaf(T[4r+2], p.z, fmaf(T[4r+1], p.y, fmaf(T[4r], p.x, T[4r+3])))
+ *   u_r = (m_r - origin[r]) / voxel   (correctly rounded)
+ *   kept iff 0 <= u_r < n_r for r = x, y, z; voxel index floorf(u_r);
+ *   occ[lin] = 1.
+ * occ is OR-ed into (call edt_clear first for a fresh map).
+ */
+int edt_insert_points(const edt_grid_t* grid, uint8_t* occ, const float* pts, int64_t n,
+                      const float* T_map_sensor, const uint8_t* exclude, void* stream);
+
+/*
+ * edt_insert_links -- insert the robot's voxelized links placed by joint
+ * state (Sec. III-A: offline link voxel models inserted according to the
+ * joint state; Alg. 2 UpdateLinks/Insert; self-collision set O_L of
+ * Eq. selfclink selected by link_mask).
+ *   link_pts  float32 [P][3], link frames, all links back to back.
+ *   link_off  HOST int32 [n_links+1]: points of link l are
+ *             link_pts[link_off[l] .. link_off[l+1]).  Non-decreasing,
+ *             link_off[0] = 0.
+ *   n_links   1..64.
+ *   link_poses float32 [n_links][12], device, row-major 3x4 link-to-map.
+ *   link_mask bit l set = insert link l.
+ * Same transform and discretisation as edt_insert_points; no exclusion.
+ */
+int edt_insert_links(const edt_grid_t* grid, uint8_t* occ, const float* link_pts,
+                     const int32_t* link_off, int32_t n_links, const float* link_poses,
+                     uint64_t link_mask, void* stream);
+
+/*
+ * edt_workspace_bytes -- device workspace edt_compute needs for this grid
+ * (0 for this version: the intermediate lives in the site output).
+ */
+size_t edt_workspace_bytes(const edt_grid_t* grid);
+
+/*
+ * edt_compute -- exact squared Euclidean distance transform with nearest
+ * sites (Sec. III-C, Alg. 1).
+ *   occ   uint8 [nx*ny*nz]; any nonzero byte is an occupied voxel (a site).
+ *   d2    int32 [nx*ny*nz] out: min over sites s of |p - s|^2 (voxel units).
+ *   site  int32 [nx*ny*nz] out: linear index of the nearest site; among
+ *         equidistant sites the smallest linear index.
+ *   If the map has no occupied voxel: d2 = INT32_MAX and site = -1
+ *   everywhere.  Both outputs are fully overwritten; they must not overlap
+ *   occ or each other.  ws / ws_bytes: workspace of at least
+ *   edt_workspace_bytes(grid) bytes (may be NULL when that is 0).
+ */
+int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * edt_query_spheres -- closest obstacle at bounding-sphere centres
+ * (Alg. 2 ExtractClosestObstaclePose; task variable x_c of Eq. dist and the
+ * constraint x_c >= radius of Eq. ref).
+ *   d2, site   outputs of edt_compute for this grid.
+ *   centres    float32 [m][3], map frame, metres.
+ *   radii      float32 [m].
+ *   out        edt_sphere_result_t [m], device.
+ * A centre outside the map gets flags EDT_Q_OUT_OF_MAP and a conservative
+ * distance of 0 (d2 = 0, site = -1, vox = -1, x_c = 0, clearance = -radius,
+ * nearest = the centre).  On an empty map flags = EDT_Q_EMPTY and the
+ * distances are +inf.  Float op order is fixed: O_a = fmaf(s_a + 0.5, voxel,
+ * origin_a); x_c = sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx*dx))) with d = O - C.
+ */
+int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* site,
+                      const float* centres, const float* radii, int32_t m,
+                      edt_sphere_result_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDTMI_EDT_H */

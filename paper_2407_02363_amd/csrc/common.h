@@ -1,0 +1,49 @@
+// Internal helpers shared by the library's translation units (not exported).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "edt.h"
+
+namespace edtmi {
+
+// Last error message of the calling thread.
+void set_error(const char* fmt, ...);
+void clear_error();
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Validates a grid; sets the error message and returns a status.
+int check_grid(const edt_grid_t* g);
+
+inline int64_t grid_voxels(const edt_grid_t* g)
+{
+    return (int64_t)g->nx * g->ny * g->nz;
+}
+
+// Checks the launch that was just enqueued.
+inline int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: launch failed: %s", what, hipGetErrorString(e));
+        return EDT_ERR_HIP;
+    }
+    return EDT_OK;
+}
+
+// Work-group index remap so that consecutive logical tiles land on the same
+// XCD (the dispatcher deals work-groups to the 8 XCDs round-robin).  A
+// bijection of [0, G).
+__device__ inline int xcd_remap(int b, int G)
+{
+    const int per = G >> 3, rem = G & 7, xcd = b & 7, k = b >> 3;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+}  // namespace edtmi

@@ -1,0 +1,102 @@
+"""GPU parity of edt_compute against the CPU oracle: bit-exact int32 d2 and
+nearest-site index, on the seeded workloads and on edge cases (empty, full,
+single site, degenerate lines, ragged dims that leave partial tiles, dims
+that select every tile width and the 64-bit envelope path)."""
+import numpy as np
+import pytest
+
+from paper_2407_02363_amd import inputs
+from tests.gpu_util import gpu_edt, say
+
+pytestmark = pytest.mark.gpu
+
+
+def assert_same(occ, oracle_lib, tag):
+    say(f"[edt parity] {tag} shape={occ.shape}")
+    d2, site = gpu_edt(occ)
+    rd2, rsite = oracle_lib.edt(occ)
+    bad_d = int((d2 != rd2).sum())
+    bad_s = int((site != rsite).sum())
+    assert bad_d == 0 and bad_s == 0, f"{tag}: {bad_d} d2 and {bad_s} site mismatches"
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_boxes_64cubed(oracle_lib, seed):
+    assert_same(inputs.boxes_grid(64, seed=seed), oracle_lib, f"boxes64 seed{seed}")
+
+
+@pytest.mark.parametrize("density", [0.001, 0.02, 0.3, 0.7])
+def test_random_16cubed_and_brute(oracle_lib, density):
+    from oracle.brute import brute_edt
+    occ = inputs.random_grid((16, 16, 16), density, 3)
+    d2, site = gpu_edt(occ)
+    bd, bs = brute_edt(occ)
+    assert np.array_equal(d2, bd) and np.array_equal(site, bs)
+
+
+SHAPES = [
+    (1, 1, 1), (1, 1, 17), (1, 17, 1), (17, 1, 1), (3, 5, 7), (2, 1, 130),
+    (65, 63, 70),        # ragged tiles in x, odd band lengths
+    (40, 257, 100),      # ny > 256: 32-wide xy tiles
+    (129, 30, 66),       # nz > 128: 32-wide z tiles
+    (300, 20, 129),      # nz > 256: 16-wide z tiles
+    (20, 520, 33),       # ny > 512: 16-wide xy tiles, 64-bit envelope test
+    (700, 9, 11),        # nz > 512: 8-wide z tiles, 64-bit envelope test
+    (7, 6, 1000),        # nx > 512: many words per row, 64-bit envelope test
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("density", [0.0005, 0.05])
+def test_random_shapes(oracle_lib, shape, density):
+    occ = inputs.random_grid(shape, density, sum(shape))
+    assert_same(occ, oracle_lib, f"random d={density}")
+
+
+def test_empty_full_single(oracle_lib):
+    assert_same(np.zeros((33, 70, 65), np.uint8), oracle_lib, "empty")
+    assert_same(np.ones((9, 70, 65), np.uint8), oracle_lib, "full")
+    for s in [(0, 0, 0), (64, 69, 32), (17, 3, 20)]:
+        assert_same(inputs.single_site_grid((33, 70, 65), s), oracle_lib, f"single {s}")
+
+
+def test_extreme_axes_1024(oracle_lib):
+    """Longest axes the API allows (keys up to ~1023^2): a site at each end of
+    a 1024-long line, and a lone site at the far end."""
+    for shape, s in [((1, 1, 1024), (1023, 0, 0)), ((1, 1024, 2), (1, 1023, 0)),
+                     ((1024, 1, 3), (2, 0, 1023))]:
+        occ = inputs.single_site_grid(shape, s)
+        assert_same(occ, oracle_lib, f"lone site {shape}")
+        occ.reshape(-1)[0] = 1
+        assert_same(occ, oracle_lib, f"two ends {shape}")
+
+
+def test_two_far_corners_wide(oracle_lib):
+    """Two sites at opposite corners of a 600 x 600 x 8 map: large keys and
+    position gaps on every axis (64-bit envelope test)."""
+    occ = np.zeros((8, 600, 600), np.uint8)
+    occ[0, 0, 0] = 1
+    occ[7, 599, 599] = 1
+    occ[3, 599, 0] = 1
+    assert_same(occ, oracle_lib, "far corners")
+
+
+def test_control_cycle_map(oracle_lib):
+    """256 x 256 x 128 map from the synthetic depth camera (1 cm voxels)."""
+    ci = inputs.cycle_inputs(0, n_frames=1)
+    occ = np.zeros(ci.grid.shape, np.uint8)
+    oracle_lib.insert_points(ci.grid, occ, ci.frames[0], ci.T_map_cam)
+    assert_same(occ, oracle_lib, "cycle map")
+
+
+def test_large_blobs_512(oracle_lib):
+    """512^3 at 5% clustered-blob occupancy, the large-map workload."""
+    occ = inputs.blobs_grid(512)
+    assert_same(occ, oracle_lib, "blobs512")
+
+
+def test_deterministic(oracle_lib):
+    occ = inputs.boxes_grid(64, seed=9)
+    a = gpu_edt(occ)
+    b = gpu_edt(occ)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
