@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the distance-map hot path on one MI355X.
+
+A step is one control cycle of Alg. 2 on the 256 x 256 x 128 map at 1 cm:
+clear the self and environment maps, insert the 8 capsule links at the
+cycle's joint state, insert a 307,200-point depth frame (robot voxels
+excluded), compute the exact EDT of both maps, and query 20 sphere centres
+in both.  Inputs are resident in device memory before timing starts.
+
+Printed as one JSON line:
+  value        EDT voxels per second over whole cycles (2 maps per cycle),
+               in Mvoxels/s -- insert, clear and query time included.
+  latency      p50 / p99 of the per-cycle latency over >= 1000 cycles, host
+               clock from enqueue to the sphere results landing in host
+               memory, plain per-map launches and graph-replayed cycles.
+  roofline     the dominant EDT kernel: algorithmic bytes / its average
+               duration (HIP events on its own stream) against 8 TB/s.
+  cpu_baseline the CPU oracle on a bounded sample of the same cycles.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "EDT Mvoxels/s + % HBM roofline; p50/p99 insert→EDT→query cycle latency"
+# algorithmic bytes per voxel of each EDT kernel (HBM in + out)
+XY_BYTES_PER_VOXEL = 1 + 4      # occupancy byte in, packed 2D site out
+Z_BYTES_PER_VOXEL = 4 + 8       # packed 2D site in, d2 + site out
+EDT_BYTES_PER_VOXEL = 9         # compulsory: occupancy in, d2 + site out
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def time_stage(edt, torch, grid, occ, d2, site, stage, reps):
+    """Average duration (ms) of one EDT stage over reps launches, HIP events
+    recorded on the stream the kernel runs on."""
+    st = torch.cuda.current_stream()
+    for _ in range(5):
+        edt.edt_compute_stage(grid, occ, d2, site, stage)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        edt.edt_compute_stage(grid, occ, d2, site, stage)
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def cpu_baseline(ci, budget_s: float):
+    """Oracle cycles on the host until ~budget_s of CPU work is done."""
+    import oracle
+    from paper_2407_02363_amd import inputs
+    g = ci.grid
+    n_cycles = 0
+    t0 = time.perf_counter()
+    while True:
+        k = n_cycles
+        q = ci.joint_states[k % len(ci.joint_states)]
+        poses = ci.robot.poses12(q)
+        occ_s = np.zeros(g.shape, np.uint8)
+        oracle.insert_links(g, occ_s, ci.link_pts, ci.link_off, poses, 0xFF)
+        occ_e = np.zeros(g.shape, np.uint8)
+        oracle.insert_points(g, occ_e, ci.frames[k % len(ci.frames)], ci.T_map_cam, exclude=occ_s)
+        d2e, se = oracle.edt(occ_e)
+        d2s, ss = oracle.edt(occ_s)
+        C = inputs.sphere_centres(ci.robot, q, ci.sphere_links, ci.sphere_local)
+        oracle.query_spheres(g, d2e, se, C, ci.sphere_radii)
+        oracle.query_spheres(g, d2s, ss, C, ci.sphere_radii)
+        n_cycles += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s and n_cycles >= 2:
+            break
+    vox = 2 * g.n * n_cycles
+    return {"value": vox / el / 1e6, "unit": "Mvoxels/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{n_cycles} full control cycles (2 maps of 256x256x128 each) in {el:.1f} s",
+            "ms_per_cycle": 1e3 * el / n_cycles}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--latency-cycles", type=int, default=1000)
+    ap.add_argument("--graphs", type=int, default=8, help="graph slots (0 = skip graph cycle)")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--frames", type=int, default=8)
+    ap.add_argument("--states", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the distance map of one "
+                          "robot is a single-GPU workload (see the design notes on sharding)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2407_02363_amd import edt, inputs
+    from paper_2407_02363_amd.cycle import ControlCycle
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    edt.lib()
+    dev = torch.device("cuda:0")
+    log("[bench] generating inputs")
+    ci = inputs.cycle_inputs(0, n_frames=args.frames, n_states=args.states)
+    cyc = ControlCycle(ci, dev)
+    g = ci.grid
+    st = torch.cuda.current_stream()
+
+    log("[bench] warmup")
+    for k in range(args.warmup):
+        cyc.run(k)
+    torch.cuda.synchronize()
+
+    # ---- throughput: K cycles back to back
+    log(f"[bench] timing {args.steps} cycles")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        cyc.run(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+    value = cyc.voxels_per_cycle * args.steps / el / 1e6
+
+    # ---- latency: enqueue -> results in host memory, per cycle
+    host_env = torch.empty(cyc.out_env.shape, dtype=torch.int32, pin_memory=True)
+    host_self = torch.empty(cyc.out_self.shape, dtype=torch.int32, pin_memory=True)
+
+    def latency_run(fn, n):
+        lat = []
+        for k in range(n):
+            t = time.perf_counter()
+            fn(k)
+            host_env.copy_(cyc.out_env, non_blocking=True)
+            host_self.copy_(cyc.out_self, non_blocking=True)
+            st.synchronize()
+            lat.append(1e3 * (time.perf_counter() - t))
+        return lat
+
+    log(f"[bench] latency, {args.latency_cycles} plain cycles")
+    lat_plain = latency_run(cyc.run, args.latency_cycles)
+    latency = {"plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
+                         "cycles": len(lat_plain)}}
+    if args.graphs > 0:
+        log(f"[bench] capturing {args.graphs} cycle graphs")
+        graphs = cyc.capture_graphs(args.graphs)
+        # check the replayed cycle against an eager run of the same slot
+        cyc.run(1)
+        torch.cuda.synchronize()
+        ref = (cyc.d2_env.clone(), cyc.site_env.clone(), cyc.out_env.clone(), cyc.out_self.clone())
+        graphs[1].replay()
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, b) for a, b in
+                   zip(ref, (cyc.d2_env, cyc.site_env, cyc.out_env, cyc.out_self)))
+        if not same:
+            raise SystemExit("graph replay differs from the eager cycle")
+        for k in range(args.warmup):
+            graphs[k % len(graphs)].replay()
+        lat_graph = latency_run(lambda k: graphs[k % len(graphs)].replay(), args.latency_cycles)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            graphs[k % len(graphs)].replay()
+        torch.cuda.synchronize()
+        el_g = time.perf_counter() - t0
+        latency["graph"] = {"p50_ms": pct(lat_graph, 50), "p99_ms": pct(lat_graph, 99),
+                            "cycles": len(lat_graph),
+                            "throughput_mvox_s": cyc.voxels_per_cycle * args.steps / el_g / 1e6,
+                            "ms_per_cycle": 1e3 * el_g / args.steps}
+
+    # ---- per-kernel timing and roofline on the environment map
+    log("[bench] per-kernel timing")
+    cyc.run(0)
+    torch.cuda.synchronize()
+    occ, d2, site = cyc.occ_env, cyc.d2_env, cyc.site_env
+    t_xy = time_stage(edt, torch, g, occ, d2, site, edt.STAGE_XY, args.kernel_reps)
+    t_z = time_stage(edt, torch, g, occ, d2, site, edt.STAGE_Z, args.kernel_reps)
+    t_all = time_stage(edt, torch, g, occ, d2, site, edt.STAGE_ALL, args.kernel_reps)
+    nvox = g.n
+    kernels = {
+        "k_edt_xy": {"avg_us": 1e3 * t_xy, "bytes_per_voxel": XY_BYTES_PER_VOXEL},
+        "k_edt_z": {"avg_us": 1e3 * t_z, "bytes_per_voxel": Z_BYTES_PER_VOXEL},
+    }
+    for k in kernels.values():
+        k["achieved_GBs"] = k["bytes_per_voxel"] * nvox / (k["avg_us"] * 1e-6) / 1e9
+    dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
+    kd = kernels[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBs"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["achieved_GBs"] / HBM_PEAK_GBS,
+                "traffic": None,
+                "algorithmic_bytes_per_launch": kd["bytes_per_voxel"] * nvox}
+    edt_alg = EDT_BYTES_PER_VOXEL * nvox / (t_all * 1e-3) / 1e9
+    edt_only = {"avg_us": 1e3 * t_all, "mvox_s": nvox / (t_all * 1e-3) / 1e6,
+                "algorithmic_GBs_9B": edt_alg, "frac_9B": edt_alg / HBM_PEAK_GBS}
+
+    out = {"metric": METRIC, "value": value, "unit": "Mvoxels/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic",
+           "config": {"workload": "control cycle, 256x256x128 map at 1 cm: clear 2 maps, insert 8 "
+                                  "capsule links (self map), insert a 307200-point depth frame "
+                                  "(robot voxels excluded), exact EDT of both maps, 20 sphere "
+                                  "queries per map",
+                      "grid": [g.nx, g.ny, g.nz], "maps_per_cycle": 2,
+                      "points_per_frame": int(ci.frames[0].shape[0]),
+                      "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
+           "latency": latency, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
+           "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",
+                             "workload": "live camera scene, 256x256x128 at 1 cm"}}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(ci, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -141,6 +141,21 @@ int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t
                 void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * edt_compute_stage -- run one pass of edt_compute, for profiling and for
+ * callers that pipeline the passes of several maps.
+ *   stage EDT_STAGE_XY: steps 1-3 of Alg. 1 in every z slice; writes the 2D
+ *         nearest site of each voxel, packed x' | y' << 16 (0xFFFFFFFF if the
+ *         slice is empty), into site; d2 is not touched.
+ *   stage EDT_STAGE_Z: step 4 (steps 2-3 along z); reads that packed form
+ *         from site and overwrites d2 and site with the final result.
+ *   stage EDT_STAGE_ALL: both, identical to edt_compute.
+ * Same arguments and errors as edt_compute otherwise.
+ */
+enum { EDT_STAGE_XY = 1, EDT_STAGE_Z = 2, EDT_STAGE_ALL = 3 };
+int edt_compute_stage(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                      void* ws, size_t ws_bytes, int stage, void* stream);
+
+/*
  * edt_query_spheres -- closest obstacle at bounding-sphere centres
  * (Alg. 2 ExtractClosestObstaclePose; task variable x_c of Eq. dist and the
  * constraint x_c >= radius of Eq. ref).

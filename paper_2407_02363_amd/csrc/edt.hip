@@ -695,21 +695,34 @@ size_t edt_workspace_bytes(const edt_grid_t* grid)
     return 0;
 }
 
-int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
-                void* ws, size_t ws_bytes, void* stream)
+int edt_compute_stage(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                      void* ws, size_t ws_bytes, int stage, void* stream)
 {
     (void)ws;
     (void)ws_bytes;
     int rc = check_grid(grid);
     if (rc) return rc;
-    if (!occ || !d2 || !site) {
+    if (stage < EDT_STAGE_XY || stage > EDT_STAGE_ALL) {
+        set_error("edt_compute_stage: bad stage %d", stage);
+        return EDT_ERR_ARG;
+    }
+    if (!site || ((stage & EDT_STAGE_XY) && !occ) || ((stage & EDT_STAGE_Z) && !d2)) {
         set_error("edt_compute: NULL occ, d2 or site");
         return EDT_ERR_ARG;
     }
     const hipStream_t st = as_stream(stream);
-    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), st);
-    if (rc) return rc;
-    return launch_edt_z(grid, d2, site, st);
+    if (stage & EDT_STAGE_XY) {
+        rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), st);
+        if (rc) return rc;
+    }
+    if (stage & EDT_STAGE_Z) rc = launch_edt_z(grid, d2, site, st);
+    return rc;
+}
+
+int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                void* ws, size_t ws_bytes, void* stream)
+{
+    return edt_compute_stage(grid, occ, d2, site, ws, ws_bytes, EDT_STAGE_ALL, stream);
 }
 
 int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* site,

@@ -1,0 +1,90 @@
+"""One control cycle of Alg. 2 on the GPU, driven through the C-ABI binding.
+
+Per cycle: ClearMap of the self map M_S and the environment map M_I; insert
+the robot links placed by the cycle's joint state into M_S; insert the
+cycle's point cloud into M_I, skipping voxels M_S occupies (Sec. III-A);
+compute the exact EDT of both maps; extract the closest obstacle at each
+sphere centre in both maps.  Only orchestration lives here: every step is
+a library call, and all inputs are staged in device memory beforehand.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import edt
+
+
+class ControlCycle:
+    def __init__(self, ci, device="cuda:0", self_mask: int = 0xFF, centres=None):
+        """ci: inputs.CycleInputs.  centres: float32 [S, m, 3] per joint
+        state (computed from ci.joint_states by forward kinematics if None)."""
+        from . import inputs
+        self.ci = ci
+        self.grid = ci.grid
+        self.dev = torch.device(device)
+        self.self_mask = int(self_mask)
+        n = ci.grid.n
+        d = self.dev
+        self.occ_self = torch.zeros(n, dtype=torch.uint8, device=d)
+        self.occ_env = torch.zeros(n, dtype=torch.uint8, device=d)
+        self.d2_self = torch.empty(n, dtype=torch.int32, device=d)
+        self.site_self = torch.empty(n, dtype=torch.int32, device=d)
+        self.d2_env = torch.empty(n, dtype=torch.int32, device=d)
+        self.site_env = torch.empty(n, dtype=torch.int32, device=d)
+        self.frames = torch.from_numpy(np.stack(ci.frames)).to(d)           # [F, n, 3]
+        self.T = torch.from_numpy(ci.T_map_cam).to(d)
+        self.link_pts = torch.from_numpy(ci.link_pts).to(d)
+        self.link_off = np.asarray(ci.link_off, np.int32)
+        states = ci.joint_states
+        self.poses = torch.from_numpy(np.stack([ci.robot.poses12(q) for q in states])).to(d)
+        if centres is None:
+            centres = np.stack([inputs.sphere_centres(ci.robot, q, ci.sphere_links, ci.sphere_local)
+                                for q in states])
+        self.centres_host = centres
+        self.centres = torch.from_numpy(np.ascontiguousarray(centres, np.float32)).to(d)
+        self.radii = torch.from_numpy(np.asarray(ci.sphere_radii, np.float32)).to(d)
+        m = self.radii.numel()
+        self.out_env = edt.new_query_out(m, d)
+        self.out_self = edt.new_query_out(m, d)
+        self.n_frames = self.frames.shape[0]
+        self.n_states = self.poses.shape[0]
+
+    @property
+    def voxels_per_cycle(self) -> int:
+        return 2 * self.grid.n
+
+    def run(self, k: int, stream=None):
+        """Enqueue cycle k (frame k mod F, joint state k mod S)."""
+        g = self.grid
+        f = k % self.n_frames
+        s = k % self.n_states
+        edt.edt_clear(g, self.occ_self, stream)
+        edt.edt_clear(g, self.occ_env, stream)
+        edt.edt_insert_links(g, self.occ_self, self.link_pts, self.link_off, self.poses[s],
+                             self.self_mask, stream)
+        edt.edt_insert_points(g, self.occ_env, self.frames[f], self.T, exclude=self.occ_self,
+                              stream=stream)
+        edt.edt_compute(g, self.occ_env, self.d2_env, self.site_env, stream=stream)
+        edt.edt_compute(g, self.occ_self, self.d2_self, self.site_self, stream=stream)
+        edt.edt_query_spheres(g, self.d2_env, self.site_env, self.centres[s], self.radii,
+                              self.out_env, stream)
+        edt.edt_query_spheres(g, self.d2_self, self.site_self, self.centres[s], self.radii,
+                              self.out_self, stream)
+
+    def capture_graphs(self, n_graphs: int):
+        """One HIP graph per (frame, state) slot k < n_graphs, each replaying
+        the whole cycle k; warm-up runs first so nothing initialises inside
+        the capture."""
+        torch.cuda.synchronize(self.dev)
+        for k in range(min(n_graphs, 3)):
+            self.run(k)
+        torch.cuda.synchronize(self.dev)
+        graphs = []
+        for k in range(n_graphs):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, capture_error_mode="thread_local"):
+                self.run(k)
+            graphs.append(g)
+        torch.cuda.synchronize(self.dev)
+        return graphs

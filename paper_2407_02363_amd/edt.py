@@ -45,7 +45,9 @@ SPHERE_RESULT_WORDS = SPHERE_RESULT_BYTES // 4
 
 EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_insert_points", "edt_insert_links", "edt_workspace_bytes", "edt_compute",
-            "edt_query_spheres"]
+            "edt_query_spheres", "edt_compute_stage"]
+
+STAGE_XY, STAGE_Z, STAGE_ALL = 1, 2, 3
 
 
 def lib():
@@ -69,6 +71,7 @@ def lib():
         "edt_workspace_bytes": ([G], ctypes.c_size_t),
         "edt_compute": ([G, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_query_spheres": ([G, P, P, P, P, i32, P, P], ctypes.c_int),
+        "edt_compute_stage": ([G, P, P, P, P, ctypes.c_size_t, ctypes.c_int, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -163,6 +166,18 @@ def edt_compute(grid, occ, d2, site, ws=None, stream=None):
                              None if ws is None else ctypes.c_void_p(ws.data_ptr()), wsb,
                              _stream(stream)),
            "edt_compute")
+
+
+def edt_compute_stage(grid, occ, d2, site, stage: int, ws=None, stream=None):
+    g = make_grid(grid)
+    n = _n(g)
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().edt_compute_stage(ctypes.byref(g), _dev(occ, torch.uint8, "occ", n),
+                                   _dev(d2, torch.int32, "d2", n),
+                                   _dev(site, torch.int32, "site", n),
+                                   None if ws is None else ctypes.c_void_p(ws.data_ptr()), wsb,
+                                   int(stage), _stream(stream)),
+           "edt_compute_stage")
 
 
 def edt_query_spheres(grid, d2, site, centres, radii, out, stream=None):
