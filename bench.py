@@ -48,19 +48,23 @@ def pct(xs, q):
 
 
 def time_stage(edt, torch, grid, occ, d2, site, stage, reps):
-    """Average duration (ms) of one EDT stage over reps launches, HIP events
-    recorded on the stream the kernel runs on."""
+    """Average duration (ms) of one EDT stage over reps launches, each
+    bracketed by HIP events recorded on the stream the kernel runs on.  The
+    z stage rewrites its input in place, so an untimed xy stage refreshes
+    that input before every timed z launch."""
     st = torch.cuda.current_stream()
-    for _ in range(5):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for i in range(reps + 3):
+        if stage == edt.STAGE_Z:
+            edt.edt_compute_stage(grid, occ, d2, site, edt.STAGE_XY)
+        if i >= 3:
+            ev[i - 3][0].record(st)
         edt.edt_compute_stage(grid, occ, d2, site, stage)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(st)
-    for _ in range(reps):
-        edt.edt_compute_stage(grid, occ, d2, site, stage)
-    b.record(st)
-    b.synchronize()
-    return a.elapsed_time(b) / reps
+        if i >= 3:
+            ev[i - 3][1].record(st)
+    st.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps
 
 
 def cpu_baseline(ci, budget_s: float):

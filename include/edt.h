@@ -141,19 +141,56 @@ int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t
                 void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Tile widths of the two EDT kernels: columns per 256-thread work-group.
+ * Each column of a tile is split into 256 / tile bands, the m2 / m3 bands
+ * of the paper's steps 2 and 3 (Sec. III-C): every band builds its own
+ * envelope of proximate sites, neighbouring envelopes are merged, and every
+ * band queries its own positions.  xy_tile is one of 16, 32, 64; z_tile one
+ * of 8, 16, 32, 64; a tile whose work-group would need more local memory
+ * than the device has is rejected with EDT_ERR_UNSUPPORTED.  Results do
+ * not depend on the tiles.
+ */
+typedef struct edt_tuning_t {
+    int32_t xy_tile;
+    int32_t z_tile;
+} edt_tuning_t;
+
+/* Tiles edt_compute uses for this grid: the autotuner's choice if
+ * edt_autotune ran for this shape in this process, else a heuristic. */
+int edt_default_tuning(const edt_grid_t* grid, edt_tuning_t* out);
+
+/* edt_compute with explicit tiles (NULL = edt_default_tuning). */
+int edt_compute_tuned(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                      const edt_tuning_t* tuning, void* stream);
+
+/*
  * edt_compute_stage -- run one pass of edt_compute, for profiling and for
  * callers that pipeline the passes of several maps.
- *   stage EDT_STAGE_XY: steps 1-3 of Alg. 1 in every z slice; writes the 2D
- *         nearest site of each voxel, packed x' | y' << 16 (0xFFFFFFFF if the
- *         slice is empty), into site; d2 is not touched.
+ *   stage EDT_STAGE_XY: steps 1-3 of Sec. III-C in every z slice; writes the
+ *         2D nearest site of each voxel, packed x' | y' << 16 (0xFFFFFFFF if
+ *         the slice is empty), into site; d2 is not touched.
  *   stage EDT_STAGE_Z: step 4 (steps 2-3 along z); reads that packed form
  *         from site and overwrites d2 and site with the final result.
- *   stage EDT_STAGE_ALL: both, identical to edt_compute.
- * Same arguments and errors as edt_compute otherwise.
+ *   stage EDT_STAGE_ALL: both, identical to edt_compute_tuned.
+ *   tuning NULL = edt_default_tuning.
  */
 enum { EDT_STAGE_XY = 1, EDT_STAGE_Z = 2, EDT_STAGE_ALL = 3 };
 int edt_compute_stage(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
-                      void* ws, size_t ws_bytes, int stage, void* stream);
+                      int stage, const edt_tuning_t* tuning, void* stream);
+
+/*
+ * edt_autotune -- pick the fastest tiles for this grid shape (the band
+ * parameters m1, m2, m3 of Alg. 1 become tile widths here).  Runs every
+ * valid (xy_tile, z_tile) pair `reps` times on occ (a representative map),
+ * timing each pass with HIP events on `stream`, and records the winner in a
+ * per-process cache keyed by (nx, ny, nz) that edt_compute and
+ * edt_default_tuning consult.  Overwrites d2 and site.  Synchronises the
+ * stream, so it must not be called while a graph is being captured.
+ *   best     out (nullable): the chosen tiles.
+ *   best_us  out (nullable): the chosen tiles' time for one full transform.
+ */
+int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                 int32_t reps, edt_tuning_t* best, float* best_us, void* stream);
 
 /*
  * edt_query_spheres -- closest obstacle at bounding-sphere centres

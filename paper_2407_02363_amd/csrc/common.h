@@ -37,6 +37,19 @@ inline int check_launch(const char* what)
     return EDT_OK;
 }
 
+// Tile widths (columns per work-group) of the two EDT passes; each
+// work-group has 256 threads, so a column gets 256 / tile bands.
+struct EdtTuning {
+    int xy_tw;
+    int z_tw;
+};
+EdtTuning default_tuning(const edt_grid_t* g);   // heuristic
+EdtTuning current_tuning(const edt_grid_t* g);   // autotuned if cached, else heuristic
+bool tile_ok(int pass, int tw, const edt_grid_t* g);   // pass 1 = xy, 2 = z
+bool needs_wide(const edt_grid_t* g);
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st);
+int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, hipStream_t st);
+
 // Work-group index remap so that consecutive logical tiles land on the same
 // XCD (the dispatcher deals work-groups to the 8 XCDs round-robin).  A
 // bijection of [0, G).

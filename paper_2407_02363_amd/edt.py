@@ -40,12 +40,17 @@ class SphereResult(ctypes.Structure):
                 ("nearest", ctypes.c_float * 3), ("reserved", ctypes.c_float)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("xy_tile", ctypes.c_int32), ("z_tile", ctypes.c_int32)]
+
+
 SPHERE_RESULT_BYTES = ctypes.sizeof(SphereResult)   # 64
 SPHERE_RESULT_WORDS = SPHERE_RESULT_BYTES // 4
 
 EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_insert_points", "edt_insert_links", "edt_workspace_bytes", "edt_compute",
-            "edt_query_spheres", "edt_compute_stage"]
+            "edt_query_spheres", "edt_compute_stage", "edt_default_tuning", "edt_compute_tuned",
+            "edt_autotune"]
 
 STAGE_XY, STAGE_Z, STAGE_ALL = 1, 2, 3
 
@@ -71,7 +76,11 @@ def lib():
         "edt_workspace_bytes": ([G], ctypes.c_size_t),
         "edt_compute": ([G, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_query_spheres": ([G, P, P, P, P, i32, P, P], ctypes.c_int),
-        "edt_compute_stage": ([G, P, P, P, P, ctypes.c_size_t, ctypes.c_int, P], ctypes.c_int),
+        "edt_compute_stage": ([G, P, P, P, ctypes.c_int, ctypes.POINTER(Tuning), P], ctypes.c_int),
+        "edt_default_tuning": ([G, ctypes.POINTER(Tuning)], ctypes.c_int),
+        "edt_compute_tuned": ([G, P, P, P, ctypes.POINTER(Tuning), P], ctypes.c_int),
+        "edt_autotune": ([G, P, P, P, i32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float), P],
+                         ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -168,16 +177,52 @@ def edt_compute(grid, occ, d2, site, ws=None, stream=None):
            "edt_compute")
 
 
-def edt_compute_stage(grid, occ, d2, site, stage: int, ws=None, stream=None):
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, Tuning):
+        return ctypes.byref(t)
+    return ctypes.byref(Tuning(int(t[0]), int(t[1])))
+
+
+def edt_compute_stage(grid, occ, d2, site, stage: int, tuning=None, stream=None):
     g = make_grid(grid)
     n = _n(g)
-    wsb = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().edt_compute_stage(ctypes.byref(g), _dev(occ, torch.uint8, "occ", n),
                                    _dev(d2, torch.int32, "d2", n),
-                                   _dev(site, torch.int32, "site", n),
-                                   None if ws is None else ctypes.c_void_p(ws.data_ptr()), wsb,
-                                   int(stage), _stream(stream)),
+                                   _dev(site, torch.int32, "site", n), int(stage),
+                                   _tuning(tuning), _stream(stream)),
            "edt_compute_stage")
+
+
+def edt_compute_tuned(grid, occ, d2, site, tuning=None, stream=None):
+    g = make_grid(grid)
+    n = _n(g)
+    _check(lib().edt_compute_tuned(ctypes.byref(g), _dev(occ, torch.uint8, "occ", n),
+                                   _dev(d2, torch.int32, "d2", n),
+                                   _dev(site, torch.int32, "site", n), _tuning(tuning),
+                                   _stream(stream)),
+           "edt_compute_tuned")
+
+
+def edt_default_tuning(grid):
+    g = make_grid(grid)
+    t = Tuning()
+    _check(lib().edt_default_tuning(ctypes.byref(g), ctypes.byref(t)), "edt_default_tuning")
+    return (t.xy_tile, t.z_tile)
+
+
+def edt_autotune(grid, occ, d2, site, reps: int = 10, stream=None):
+    """Returns ((xy_tile, z_tile), microseconds of one transform)."""
+    g = make_grid(grid)
+    n = _n(g)
+    t = Tuning()
+    us = ctypes.c_float()
+    _check(lib().edt_autotune(ctypes.byref(g), _dev(occ, torch.uint8, "occ", n),
+                              _dev(d2, torch.int32, "d2", n), _dev(site, torch.int32, "site", n),
+                              int(reps), ctypes.byref(t), ctypes.byref(us), _stream(stream)),
+           "edt_autotune")
+    return (t.xy_tile, t.z_tile), float(us.value)
 
 
 def edt_query_spheres(grid, d2, site, centres, radii, out, stream=None):

@@ -79,3 +79,15 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.edt_insert_points(ctypes.byref(ok), None, None, 0, None, None, None) == 0
     assert lib.edt_query_spheres(ctypes.byref(ok), None, None, None, None, 0, None, None) == 0
     assert lib.edt_workspace_bytes(ctypes.byref(ok)) == 0
+    # tuning: defaults are valid tiles; bad tiles are rejected before launch
+    t = edt.Tuning()
+    assert lib.edt_default_tuning(ctypes.byref(ok), ctypes.byref(t)) == 0
+    assert t.xy_tile in (16, 32, 64) and t.z_tile in (8, 16, 32, 64)
+    one = ctypes.c_void_p(256)
+    bad_t = edt.Tuning(24, 8)
+    assert lib.edt_compute_tuned(ctypes.byref(ok), one, one, one, ctypes.byref(bad_t), None) == -5
+    huge = edt.EdtGrid(8, 1024, 8, (ctypes.c_float * 3)(0, 0, 0), 0.01)
+    assert lib.edt_compute_tuned(ctypes.byref(huge), one, one, one,
+                                 ctypes.byref(edt.Tuning(64, 8)), None) == -5
+    assert lib.edt_compute_stage(ctypes.byref(ok), one, one, one, 4, None, None) == -1
+    assert lib.edt_autotune(ctypes.byref(ok), one, one, one, 0, None, None, None) == -1

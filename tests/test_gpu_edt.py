@@ -100,3 +100,52 @@ def test_deterministic(oracle_lib):
     a = gpu_edt(occ)
     b = gpu_edt(occ)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("shape", [(128, 256, 256), (37, 90, 130), (64, 64, 64)])
+def test_every_tiling_is_identical(oracle_lib, shape):
+    """Tile widths (band counts) change the launch, never the result."""
+    import torch
+    from paper_2407_02363_amd import edt
+    from tests.gpu_util import dev, grid_of
+    occ = inputs.random_grid(shape, 0.003, 17)
+    occ[shape[0] // 2, :, 5] = 1
+    rd2, rsite = oracle_lib.edt(occ)
+    g = grid_of(shape)
+    o = torch.from_numpy(occ.ravel()).to(dev())
+    d2 = torch.empty(occ.size, dtype=torch.int32, device=dev())
+    site = torch.empty_like(d2)
+    for xt in (16, 32, 64):
+        for zt in (8, 16, 32, 64):
+            say(f"[tiling] {shape} xy={xt} z={zt}")
+            d2.fill_(-7)
+            site.fill_(-7)
+            try:
+                edt.edt_compute_tuned(g, o, d2, site, (xt, zt))
+            except edt.EdtError as e:
+                assert e.status == -5   # tile needs more LDS than the device has
+                continue
+            torch.cuda.synchronize()
+            assert np.array_equal(d2.cpu().numpy().reshape(shape), rd2), (xt, zt)
+            assert np.array_equal(site.cpu().numpy().reshape(shape), rsite), (xt, zt)
+
+
+def test_autotune_keeps_results(oracle_lib):
+    import torch
+    from paper_2407_02363_amd import edt
+    from tests.gpu_util import dev, grid_of
+    occ = inputs.boxes_grid(64, seed=3)
+    g = grid_of(occ.shape)
+    o = torch.from_numpy(occ.ravel()).to(dev())
+    d2 = torch.empty(occ.size, dtype=torch.int32, device=dev())
+    site = torch.empty_like(d2)
+    (xt, zt), us = edt.edt_autotune(g, o, d2, site, reps=3)
+    say(f"[autotune] 64^3 -> xy={xt} z={zt} {us:.1f} us")
+    assert us > 0 and edt.edt_default_tuning(g) == (xt, zt)
+    rd2, rsite = oracle_lib.edt(occ)
+    assert np.array_equal(d2.cpu().numpy().reshape(occ.shape), rd2)
+    d2.fill_(0)
+    edt.edt_compute(g, o, d2, site)
+    torch.cuda.synchronize()
+    assert np.array_equal(d2.cpu().numpy().reshape(occ.shape), rd2)
+    assert np.array_equal(site.cpu().numpy().reshape(occ.shape), rsite)
