@@ -16,14 +16,16 @@
 //
 // Banding (the m2 / m3 bands of the paper's steps 2 and 3).  Each column is
 // cut into NB bands; one thread per (column, band) builds the band's own
-// envelope with a stack; one thread per column then merges neighbouring
-// envelopes: the merged envelope keeps a prefix of the left one and a suffix
-// of the right one, found by popping dominated sites on either side of the
-// seam until neither side pops.  Each (column, band) thread finally locates
-// the envelope site of its first position (scan over band ranges, then a
-// binary search) and marches through its positions.  The stacks keep packed
-// self-contained entries (position | x' << 10 [| y' << 20]), so a key is
-// recomputed from an entry and no side table is needed.
+// envelope with a stack.  The band envelopes of a column are then merged in
+// log2(NB) rounds of independent pairwise merges: the envelope of two
+// neighbouring groups keeps a prefix of the left one and a suffix of the
+// right one, found by popping dominated sites on either side of the seam
+// until neither side pops.  Each (column, band) thread then locates the
+// envelope site of its first position (walking from its own band's range,
+// then a binary search) and marches through its positions with a
+// strength-reduced test.  The stacks keep packed self-contained entries
+// (position | x' << 10 [| y' << 20]), so a key is recomputed from an entry
+// and no side table is needed.
 //
 //   k_edt_xy  work-group = (z slice, TW consecutive columns).  Each wave
 //             reduces whole rows to a 64-bit ballot word for the tile plus
@@ -46,13 +48,19 @@ constexpr int NT = 256;                 // threads per work-group
 constexpr uint32_t XY_NONE = 0xFFFFFFFFu;
 constexpr uint32_t POS_MASK = 1023u;
 
+// 24-bit multiply (full rate on CDNA; v_mul_lo_u32 is quarter rate): exact
+// when both operands fit in 24 signed bits and the product in 32.
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+
+// Keys are below 3 * 1023^2 < 2^22 and position gaps below 2^10, so every
+// operand fits in 24 bits; with all axes <= 512 the products stay below 2^31.
 template <bool WIDE>
 __device__ __forceinline__ bool dominated(int pa, int ka, int pb, int kb, int pc, int kc)
 {
     if constexpr (WIDE) {
         return (int64_t)(kc - kb) * (pb - pa) <= (int64_t)(kb - ka) * (pc - pb);
     } else {
-        return (kc - kb) * (pb - pa) <= (kb - ka) * (pc - pb);
+        return mul24(kc - kb, pb - pa) <= mul24(kb - ka, pc - pb);
     }
 }
 
@@ -60,7 +68,7 @@ __device__ __forceinline__ bool dominated(int pa, int ka, int pb, int kb, int pc
 // 2^31 for positions and keys of grids up to 1024 per axis.
 __device__ __forceinline__ bool next_closer(int p0, int k0, int p1, int k1, int q)
 {
-    return k1 - 2 * q * p1 < k0 - 2 * q * p0;
+    return k1 - 2 * mul24(q, p1) < k0 - 2 * mul24(q, p0);
 }
 
 // entry of the y pass: y' | x' << 10
@@ -70,7 +78,7 @@ struct KeyY {
     {
         const int p = (int)(e & POS_MASK);
         const int d = xc - (int)(e >> 10);
-        return d * d + p * p;
+        return mul24(d, d) + mul24(p, p);
     }
 };
 
@@ -82,7 +90,7 @@ struct KeyZ {
         const int p = (int)(e & POS_MASK);
         const int dx = xc - (int)((e >> 10) & POS_MASK);
         const int dy = yc - (int)(e >> 20);
-        return dx * dx + dy * dy + p * p;
+        return mul24(dx, dx) + mul24(dy, dy) + mul24(p, p);
     }
 };
 
@@ -120,97 +128,143 @@ struct BandStack {
 struct BandMeta {
     int16_t* lo;
     int16_t* hi;
-    int16_t* nxt;
-    int16_t* first;   // [TW]: first band with a non-empty range (NB if none)
+    int16_t* nxt;     // next band with a non-empty range (NB if none)
+    int16_t* prv;     // previous band with a non-empty range (-1 if none)
 };
 
-template <int TW, int NB, bool WIDE, class KeyF>
-__device__ void merge_bands(const uint32_t* ent, int L, int col, const BandMeta& m, const KeyF& key)
+// Merge the envelope of bands [gl, gm) (already merged) with that of bands
+// [gm, gr): the result keeps a prefix of the left chain and a suffix of the
+// right one, found by popping the seam's dominated sites on either side
+// until neither side pops.  s, t are the left chain's last two sites, c, d
+// the right chain's first two; all four stay in registers.  Only this
+// thread touches bands [gl, gr) meanwhile.
+template <int TW, bool WIDE, class KeyF>
+__device__ void merge_group(const uint32_t* ent, int L, int col, const BandMeta& m, const KeyF& key,
+                            int gl, int gm, int gr)
 {
     auto E = [&](int b, int i) { return ent[(b * L + i) * TW + col]; };
     auto LO = [&](int b) -> int16_t& { return m.lo[b * TW + col]; };
     auto HI = [&](int b) -> int16_t& { return m.hi[b * TW + col]; };
-    // nearest band before b with a non-empty range (exists whenever asked)
-    auto prev_band = [&](int b) {
-        int pl = b - 1;
-        while (pl > 0 && LO(pl) == HI(pl)) --pl;
-        return pl;
+    int lastL = gm - 1;
+    while (lastL >= gl && LO(lastL) == HI(lastL)) --lastL;
+    if (lastL < gl) return;
+    int firstR = gm;
+    while (firstR < gr && LO(firstR) == HI(firstR)) ++firstR;
+    if (firstR >= gr) return;
+    int cntL = 0, cntR = 0;
+    for (int b = gl; b < gm; ++b) cntL += HI(b) - LO(b);
+    for (int b = gm; b < gr; ++b) cntR += HI(b) - LO(b);
+    int loL = LO(lastL), hiL = HI(lastL), loR = LO(firstR), hiR = HI(firstR);
+    // neighbouring non-empty bands inside the group (they exist when asked)
+    auto prevL = [&](int b) {
+        int p = b - 1;
+        while (p > gl && LO(p) == HI(p)) --p;
+        return p;
     };
-    int last = -1;        // last band with a non-empty range in the merged part
-    int loL = 0, hiL = 0; // its range (hiL cached, written back)
-    int cnt = 0;          // entries in the merged part
-    for (int b = 0; b < NB; ++b) {
-        int lob = 0;
-        const int hib = HI(b);
-        if (hib == 0) continue;
-        if (last >= 0) {
-            // the seam: s, t = last two entries of the merged part, c, d =
-            // first two of band b; all four stay in registers
-            auto second = [&]() {
-                return hiL - loL >= 2 ? E(last, hiL - 2) : E(prev_band(last), HI(prev_band(last)) - 1);
-            };
-            const uint32_t et = E(last, hiL - 1);
-            int pt = (int)(et & POS_MASK), kt = key(et);
-            int ps = 0, ks = 0;
-            if (cnt >= 2) {
-                const uint32_t es = second();
-                ps = (int)(es & POS_MASK);
-                ks = key(es);
-            }
-            const uint32_t ec = E(b, 0);
-            int pc = (int)(ec & POS_MASK), kc = key(ec);
-            int pd = 0, kd = 0;
-            if (hib >= 2) {
-                const uint32_t ed = E(b, 1);
-                pd = (int)(ed & POS_MASK);
-                kd = key(ed);
-            }
-            for (;;) {
-                if (cnt >= 2 && dominated<WIDE>(ps, ks, pt, kt, pc, kc)) {
-                    --hiL;
-                    --cnt;
-                    if (hiL == loL) {
-                        HI(last) = (int16_t)hiL;
-                        last = prev_band(last);
-                        loL = LO(last);
-                        hiL = HI(last);
-                    }
-                    pt = ps;
-                    kt = ks;
-                    if (cnt >= 2) {
-                        const uint32_t es = second();
-                        ps = (int)(es & POS_MASK);
-                        ks = key(es);
-                    }
-                    continue;
-                }
-                if (hib - lob >= 2 && dominated<WIDE>(pt, kt, pc, kc, pd, kd)) {
-                    ++lob;
-                    pc = pd;
-                    kc = kd;
-                    if (hib - lob >= 2) {
-                        const uint32_t ed = E(b, lob + 1);
-                        pd = (int)(ed & POS_MASK);
-                        kd = key(ed);
-                    }
-                    continue;
-                }
-                break;
-            }
-            HI(last) = (int16_t)hiL;
-        }
-        LO(b) = (int16_t)lob;
-        cnt += hib - lob;
-        last = b;
-        loL = lob;
-        hiL = hib;
+    auto nextR = [&](int b) {
+        int x = b + 1;
+        while (x < gr - 1 && LO(x) == HI(x)) ++x;
+        return x;
+    };
+    auto secondL = [&]() {
+        if (hiL - loL >= 2) return E(lastL, hiL - 2);
+        const int p = prevL(lastL);
+        return E(p, HI(p) - 1);
+    };
+    auto secondR = [&]() {
+        if (hiR - loR >= 2) return E(firstR, loR + 1);
+        const int x = nextR(firstR);
+        return E(x, LO(x));
+    };
+    uint32_t e = E(lastL, hiL - 1);
+    int pt = (int)(e & POS_MASK), kt = key(e);
+    int ps = 0, ks = 0;
+    if (cntL >= 2) {
+        e = secondL();
+        ps = (int)(e & POS_MASK);
+        ks = key(e);
     }
+    e = E(firstR, loR);
+    int pc = (int)(e & POS_MASK), kc = key(e);
+    int pd = 0, kd = 0;
+    if (cntR >= 2) {
+        e = secondR();
+        pd = (int)(e & POS_MASK);
+        kd = key(e);
+    }
+    for (;;) {
+        if (cntL >= 2 && dominated<WIDE>(ps, ks, pt, kt, pc, kc)) {
+            --hiL;
+            --cntL;
+            if (hiL == loL) {
+                HI(lastL) = (int16_t)hiL;
+                lastL = prevL(lastL);
+                loL = LO(lastL);
+                hiL = HI(lastL);
+            }
+            pt = ps;
+            kt = ks;
+            if (cntL >= 2) {
+                e = secondL();
+                ps = (int)(e & POS_MASK);
+                ks = key(e);
+            }
+            continue;
+        }
+        if (cntR >= 2 && dominated<WIDE>(pt, kt, pc, kc, pd, kd)) {
+            ++loR;
+            --cntR;
+            if (loR == hiR) {
+                LO(firstR) = (int16_t)loR;
+                firstR = nextR(firstR);
+                loR = LO(firstR);
+                hiR = HI(firstR);
+            }
+            pc = pd;
+            kc = kd;
+            if (cntR >= 2) {
+                e = secondR();
+                pd = (int)(e & POS_MASK);
+                kd = key(e);
+            }
+            continue;
+        }
+        break;
+    }
+    HI(lastL) = (int16_t)hiL;
+    LO(firstR) = (int16_t)loR;
+}
+
+// Links between the non-empty band ranges of one column.
+template <int TW, int NB>
+__device__ void link_bands(int col, const BandMeta& m)
+{
     int nxt = NB;
     for (int b = NB - 1; b >= 0; --b) {
         m.nxt[b * TW + col] = (int16_t)nxt;
-        if (LO(b) < HI(b)) nxt = b;
+        if (m.lo[b * TW + col] < m.hi[b * TW + col]) nxt = b;
     }
-    m.first[col] = (int16_t)nxt;
+    int prv = -1;
+    for (int b = 0; b < NB; ++b) {
+        m.prv[b * TW + col] = (int16_t)prv;
+        if (m.lo[b * TW + col] < m.hi[b * TW + col]) prv = b;
+    }
+}
+
+// All bands of every column of the tile: log2(NB) rounds of pairwise group
+// merges (groups of one round are independent), then the band links.
+template <int TW, int NB, bool WIDE, class KeyF>
+__device__ __forceinline__ void merge_all(const uint32_t* ent, int L, int col, int band, bool live,
+                                          const BandMeta& m, const KeyF& key)
+{
+    for (int half = 1; half < NB; half <<= 1) {
+        const int span = half << 1;
+        if (live && (band & (span - 1)) == 0)
+            merge_group<TW, WIDE>(ent, L, col, m, key, band, band + half, band + span);
+        __syncthreads();
+    }
+    if (live && band == col * NB / TW) link_bands<TW, NB>(col, m);
+    __syncthreads();
 }
 
 // Positions [q0, q1) of one column off the merged envelope.  The site of
@@ -229,8 +283,15 @@ __device__ __forceinline__ void query_band(const uint32_t* ent, int L, int col, 
     auto LO = [&](int b) -> int { return m.lo[b * TW + col]; };
     auto HI = [&](int b) -> int { return m.hi[b * TW + col]; };
     auto NX = [&](int b) -> int { return m.nxt[b * TW + col]; };
-    int j = m.first[col];
-    if (j >= NB) {
+    auto PV = [&](int b) -> int { return m.prv[b * TW + col]; };
+    // start from the nearest non-empty band to this one and walk to the band
+    // range holding the envelope site of q0
+    const int own = q0 / L;
+    int j;
+    if (LO(own) < HI(own)) j = own;
+    else if (NX(own) < NB) j = NX(own);
+    else if (PV(own) >= 0) j = PV(own);
+    else {
         none(q0, q1);
         return;
     }
@@ -242,6 +303,14 @@ __device__ __forceinline__ void query_band(const uint32_t* ent, int L, int col, 
             const uint32_t el = E(j, hij - 1), en = E(jn, LO(jn));
             if (next_closer((int)(el & POS_MASK), key(el), (int)(en & POS_MASK), key(en), q0)) {
                 j = jn;
+                continue;
+            }
+        }
+        const int jp = PV(j);
+        if (jp >= 0) {
+            const uint32_t el = E(jp, HI(jp) - 1), ef = E(j, LO(j));
+            if (!next_closer((int)(el & POS_MASK), key(el), (int)(ef & POS_MASK), key(ef), q0)) {
+                j = jp;
                 continue;
             }
         }
@@ -278,7 +347,7 @@ __device__ __forceinline__ void query_band(const uint32_t* ent, int L, int col, 
             pn = (int)(en & POS_MASK);
             kkn = key(en);
             dp2 = 2 * (pn - pk);
-            g = q * dp2 - (kkn - kk);
+            g = mul24(q, dp2) - (kkn - kk);
         }
     };
     load_next(q0);
@@ -343,8 +412,8 @@ __global__ __launch_bounds__(NT) void k_edt_xy(const uint8_t* __restrict__ occ,
     uint64_t* rword = reinterpret_cast<uint64_t*>(lds + ent_words);     // [ny]
     int16_t* rleft = reinterpret_cast<int16_t*>(rword + ny);            // [ny]
     int16_t* rright = rleft + ny;                                       // [ny]
-    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_first[TW];
-    const BandMeta meta{s_lo, s_hi, s_nxt, s_first};
+    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_prv[NB * TW];
+    const BandMeta meta{s_lo, s_hi, s_nxt, s_prv};
 
     const int T = xcd_remap(blockIdx.x, nz * ntx);
     const int z = T / ntx;
@@ -472,15 +541,14 @@ __global__ __launch_bounds__(NT) void k_edt_xy(const uint8_t* __restrict__ occ,
                 else xp = (xc - xl <= xr - xc) ? xl : xr;
                 if (xp < 0) continue;
                 const int d = xc - xp;
-                st.push((uint32_t)y | ((uint32_t)xp << 10), y, d * d + y * y, key);
+                st.push((uint32_t)y | ((uint32_t)xp << 10), y, mul24(d, d) + mul24(y, y), key);
             }
         }
         s_lo[band * TW + col] = 0;
         s_hi[band * TW + col] = (int16_t)st.top;
     }
     __syncthreads();
-    if (band == col * NB / TW && live) merge_bands<TW, NB, WIDE>(ent, L, col, meta, key);
-    __syncthreads();
+    merge_all<TW, NB, WIDE>(ent, L, col, band, live, meta, key);
 
     // ---- step 3: every row of the band
     if (!live || q0 >= q1) return;
@@ -506,12 +574,12 @@ __global__ __launch_bounds__(NT) void k_edt_z(int32_t* d2, int32_t* site, int nx
                                               int ntx)
 {
     constexpr int NB = NT / TW;
-    constexpr int CH = 32;  // loads in flight per thread
+    constexpr int CH = 8;   // positions per software-pipelined chunk
     extern __shared__ uint32_t lds[];
     const int L = (nz + NB - 1) / NB;
     uint32_t* ent = lds;    // [NB*L][TW]
-    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_first[TW];
-    const BandMeta meta{s_lo, s_hi, s_nxt, s_first};
+    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_prv[NB * TW];
+    const BandMeta meta{s_lo, s_hi, s_nxt, s_prv};
 
     const int T = xcd_remap(blockIdx.x, ny * ntx);
     const int y = T / ntx;
@@ -522,40 +590,45 @@ __global__ __launch_bounds__(NT) void k_edt_z(int32_t* d2, int32_t* site, int nx
     const bool live = xc < nx;
     const KeyZ key{xc, y};
     const size_t plane = (size_t)nx * ny;
+    const unsigned plane32 = (unsigned)nx * (unsigned)ny;
     const size_t base = (size_t)y * nx + xc;
     const int q0 = band * L;
     const int q1 = min(nz, q0 + L);
 
     {
         BandStack<TW, WIDE, KeyZ> st{ent + q0 * TW + col, 0, 0, 0, 0, 0};
-        if (live) {
+        if (live && q0 < q1) {
+            // chunks of CH positions, software-pipelined: the next chunk's
+            // loads (clamped into the band) are in flight while this chunk is
+            // pushed, with the chunk loop fully unrolled
+            auto load = [&](uint32_t (&v)[CH], int zb) {
+#pragma unroll
+                for (int i = 0; i < CH; ++i)   // z * plane < 2^32 with z < 2^10, plane <= 2^20
+                    v[i] = (uint32_t)site[base + __umul24((unsigned)min(zb + i, q1 - 1), plane32)];
+            };
+            uint32_t cur[CH], nxt[CH];
+            load(cur, q0);
             for (int zb = q0; zb < q1; zb += CH) {
-                // unconditional loads from clamped positions, all in flight
-                // before the first use; positions past the band are masked
-                uint32_t v[CH];
-#pragma unroll
-                for (int i = 0; i < CH; ++i)
-                    v[i] = (uint32_t)site[base + (size_t)min(zb + i, q1 - 1) * plane];
-#pragma unroll
-                for (int i = 0; i < CH; ++i)
-                    if (zb + i >= q1) v[i] = XY_NONE;
+                load(nxt, zb + CH);
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    if (v[i] == XY_NONE) continue;
                     const int zz = zb + i;
-                    const int xp = (int)(v[i] & 0xFFFFu), yp = (int)(v[i] >> 16);
-                    const int dx = xc - xp, dy = y - yp;
-                    st.push((uint32_t)zz | ((uint32_t)xp << 10) | ((uint32_t)yp << 20), zz,
-                            dx * dx + dy * dy + zz * zz, key);
+                    if (zz < q1 && cur[i] != XY_NONE) {
+                        const int xp = (int)(cur[i] & 0xFFFFu), yp = (int)(cur[i] >> 16);
+                        const int dx = xc - xp, dy = y - yp;
+                        st.push((uint32_t)zz | ((uint32_t)xp << 10) | ((uint32_t)yp << 20), zz,
+                                mul24(dx, dx) + mul24(dy, dy) + mul24(zz, zz), key);
+                    }
                 }
+#pragma unroll
+                for (int i = 0; i < CH; ++i) cur[i] = nxt[i];
             }
         }
         s_lo[band * TW + col] = 0;
         s_hi[band * TW + col] = (int16_t)st.top;
     }
     __syncthreads();
-    if (band == col * NB / TW && live) merge_bands<TW, NB, WIDE>(ent, L, col, meta, key);
-    __syncthreads();
+    merge_all<TW, NB, WIDE>(ent, L, col, band, live, meta, key);
 
     if (!live || q0 >= q1) return;
     int dd = 0, inc = 0;
@@ -566,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_edt_z(int32_t* d2, int32_t* site, int nx
         ent, L, col, meta, q0, q1, key,
         [&](int q, uint32_t e, int p, int k) {
             // along a run of one site, (q - p)^2 + h grows by 2(q - p) + 1
-            dd = k - 2 * q * p + q * q;
+            dd = k - 2 * mul24(q, p) + mul24(q, q);
             inc = 2 * (q - p) + 1;
             ss = (int32_t)(((e >> 10) & POS_MASK) + (uint32_t)nx * ((e >> 20) + (uint32_t)ny * (uint32_t)p));
         },
@@ -675,9 +748,13 @@ bool tile_ok(int pass, int tw, const edt_grid_t* g)
 
 EdtTuning default_tuning(const edt_grid_t* g)
 {
+    // measured on MI355X: 32-wide xy tiles up to 256 rows, 16-wide beyond;
+    // z tiles keep about 32 positions per band
     EdtTuning t;
-    t.xy_tw = g->ny <= 512 ? 32 : 16;
-    t.z_tw = g->nz <= 128 ? 64 : (g->nz <= 512 ? 32 : 16);
+    t.xy_tw = g->ny <= 256 ? 32 : 16;
+    t.z_tw = g->nz <= 128 ? 64 : (g->nz <= 256 ? 32 : 16);
+    if (!tile_ok(1, t.xy_tw, g)) t.xy_tw = 16;
+    if (!tile_ok(2, t.z_tw, g)) t.z_tw = 8;
     return t;
 }
 
