@@ -193,6 +193,56 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
                  int32_t reps, edt_tuning_t* best, float* best_us, void* stream);
 
 /*
+ * ---- batches of maps ----
+ * Many maps of uneven size -- a fleet of robots, or one robot's maps at
+ * several look-ahead states -- transformed in ONE persistent launch: the
+ * xy tiles of every map, then the z tiles of every map, form a work queue
+ * that resident work-groups drain; a map's z tiles wait (device-scope
+ * acquire on a per-map counter) until all its xy tiles are released.
+ * Results are identical to edt_compute on each map.
+ */
+#define EDT_BATCH_MAX 48
+
+typedef struct edt_batch_map_t {
+    edt_grid_t grid;      /* every axis <= 512 voxels */
+    const uint8_t* occ;   /* device, as for edt_compute */
+    int32_t* d2;          /* device out */
+    int32_t* site;        /* device out */
+} edt_batch_map_t;
+
+/* Workspace bytes for a batch of n_maps (queue head, error flag, one
+ * counter per map). */
+size_t edt_batch_workspace_bytes(int32_t n_maps);
+
+/*
+ * edt_compute_batched -- exact EDT of every map of the batch.
+ *   maps    HOST array of n_maps (1..EDT_BATCH_MAX) descriptors; buffers of
+ *           different maps must not overlap.  The array is read during the
+ *           call (its contents become kernel arguments), so a captured graph
+ *           replays the same buffers.
+ *   ws      device workspace of edt_batch_workspace_bytes(n_maps) bytes,
+ *           zeroed by the call itself (a fill kernel, no memset node); two
+ *           batches in flight at once need two workspaces.
+ *   tuning  NULL = the batch autotuner's choice for this shape class, else
+ *           xy_tile in {16, 32}, z_tile in {16, 32, 64}.
+ * Errors: EDT_ERR_UNSUPPORTED for an axis above 512 or tiles that do not
+ * fit; argument errors as for edt_compute.
+ */
+int edt_compute_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t ws_bytes,
+                        const edt_tuning_t* tuning, void* stream);
+
+/* Synchronises the stream and reports whether a batch launch that used ws
+ * gave up waiting for a map's xy tiles (*timed_out = 1: that map's result
+ * is incomplete).  Never expected; a guard against a stuck queue. */
+int edt_batch_status(const void* ws, int32_t* timed_out, void* stream);
+
+/* Times every batch tile pair on this batch (reps launches each, HIP
+ * events), caches the fastest for batches with the same count and maximum
+ * dimensions, and leaves its result in the outputs.  Synchronises. */
+int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t ws_bytes,
+                         int32_t reps, edt_tuning_t* best, float* best_us, void* stream);
+
+/*
  * edt_query_spheres -- closest obstacle at bounding-sphere centres
  * (Alg. 2 ExtractClosestObstaclePose; task variable x_c of Eq. dist and the
  * constraint x_c >= radius of Eq. ref).

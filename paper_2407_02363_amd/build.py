@@ -28,20 +28,42 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build_library(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
+    return res.returncode, out
+
+
+def build_library(verbose: bool = False) -> str:
+    """Compile each source to an object in parallel, then link the library."""
+    from concurrent.futures import ThreadPoolExecutor
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    cflags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for src in sources():
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        jobs.append((src, obj, [hipcc, *cflags, *inc, "-c", "-o", obj, src]))
+    if verbose:
+        for _, _, cmd in jobs:
+            print(" ".join(cmd), flush=True)
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda j: _run(j[2]), jobs))
+    for (src, _, _), (rc, out) in zip(jobs, results):
+        if rc != 0:
+            sys.stderr.write(out + "\n")
+            raise RuntimeError(f"hipcc failed on {os.path.basename(src)}")
+        if verbose and out.strip():
+            print(out)
+    tmp = LIB + ".tmp"
+    rc, out = _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
+                    *[j[1] for j in jobs]])
+    if rc != 0:
         sys.stderr.write(out + "\n")
-        raise RuntimeError("hipcc failed building libedtmi.so")
-    if verbose and out.strip():
-        print(out)
+        raise RuntimeError("linking libedtmi.so failed")
     os.replace(tmp, LIB)
     return LIB
 

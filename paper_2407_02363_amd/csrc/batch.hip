@@ -1,0 +1,402 @@
+// Many maps of uneven size in one persistent launch.
+//
+// The work of a batch is a queue of tiles: every xy tile of every map, then
+// every z tile of every map.  Work-groups stay resident and take the next
+// tile from a global counter until the queue is empty.  A map's z tiles need
+// all of its xy tiles: each finished xy tile raises the map's counter with a
+// release (device scope), and a work-group that takes a z tile waits until
+// the counter is complete with an acquire.  Every xy tile is dequeued before
+// any z tile and is being processed by a resident work-group, so the waits
+// always end; they are still bounded by a spin limit, past which the tile is
+// skipped and an error flag is raised in the workspace (edt_batch_status).
+//
+// Workspace (unsigned words): [0] queue head, [1] error flag,
+// [2 + m] finished xy tiles of map m.  A small fill kernel zeroes it before
+// every launch, so the pair of launches can be captured into a graph.
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "edt_tiles.h"
+
+namespace edtmi {
+
+namespace {
+
+using namespace tiles;
+
+struct MapDesc {
+    int nx, ny, nz;
+    int ntx_xy, ntx_z;       // column tiles per slice / per row
+    int xy_begin, xy_count;  // queue range of the map's xy tiles
+    int z_begin;             // queue start of its z tiles
+    int fast;                // 16-byte row path usable
+    const uint8_t* occ;
+    int32_t* d2;
+    int32_t* site;
+};
+
+struct BatchArgs {
+    int n_maps;
+    int n_xy;       // xy tiles of all maps (they come first in the queue)
+    int n_total;    // all tiles
+    MapDesc m[EDT_BATCH_MAX];
+};
+
+constexpr int WS_HEAD = 0, WS_ERR = 1, WS_DONE = 2;
+
+__global__ void k_batch_reset(unsigned* ws, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ws[i] = 0u;
+}
+
+template <int TXY, int TZ, int NWMAX>
+__global__ __launch_bounds__(NT) void k_edt_batched(BatchArgs a, unsigned* ws, unsigned spin_limit)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_item;
+    __shared__ int s_ok;
+    for (;;) {
+        __syncthreads();   // the previous tile's LDS reads are done
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&ws[WS_HEAD], 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= a.n_total) break;
+        if (it < a.n_xy) {
+            int m = 0;
+            while (m + 1 < a.n_maps && a.m[m + 1].xy_begin <= it) ++m;
+            const MapDesc& d = a.m[m];
+            uint32_t* xy = reinterpret_cast<uint32_t*>(d.site);
+            if (d.fast)
+                edt_xy_tile<TXY, false, NWMAX, true>(d.occ, xy, d.nx, d.ny, d.nz, d.ntx_xy,
+                                                     it - d.xy_begin, lds);
+            else
+                edt_xy_tile<TXY, false, NWMAX, false>(d.occ, xy, d.nx, d.ny, d.nz, d.ntx_xy,
+                                                      it - d.xy_begin, lds);
+            __syncthreads();   // every thread's stores of this tile are issued
+            if (threadIdx.x == 0) {
+                __threadfence();
+                atomicAdd(&ws[WS_DONE + m], 1u);
+            }
+        } else {
+            int m = 0;
+            while (m + 1 < a.n_maps && a.m[m + 1].z_begin <= it) ++m;
+            const MapDesc& d = a.m[m];
+            if (threadIdx.x == 0) {
+                int ok = 1;
+                unsigned spins = 0;
+                while (__hip_atomic_load(&ws[WS_DONE + m], __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) < (unsigned)d.xy_count) {
+                    __builtin_amdgcn_s_sleep(8);
+                    if (++spins > spin_limit) {
+                        ok = 0;
+                        atomicOr(&ws[WS_ERR], 1u);
+                        break;
+                    }
+                }
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (s_ok) edt_z_tile<TZ, false>(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx_z, it - d.z_begin, lds);
+        }
+    }
+}
+
+struct BatchPlan {
+    BatchArgs args;
+    int nx_max, ny_max, nz_max;
+};
+
+int make_plan(const edt_batch_map_t* maps, int n, int txy, int tz, BatchPlan& p)
+{
+    p.args.n_maps = n;
+    p.nx_max = p.ny_max = p.nz_max = 0;
+    int q = 0;
+    for (int i = 0; i < n; ++i) {
+        const edt_grid_t* g = &maps[i].grid;
+        int rc = check_grid(g);
+        if (rc) return rc;
+        if (g->nx > 512 || g->ny > 512 || g->nz > 512) {
+            set_error("edt_compute_batched: map %d has an axis above 512 voxels", i);
+            return EDT_ERR_UNSUPPORTED;
+        }
+        if (!maps[i].occ || !maps[i].d2 || !maps[i].site) {
+            set_error("edt_compute_batched: NULL buffer in map %d", i);
+            return EDT_ERR_ARG;
+        }
+        MapDesc& d = p.args.m[i];
+        d.nx = g->nx;
+        d.ny = g->ny;
+        d.nz = g->nz;
+        d.ntx_xy = (g->nx + txy - 1) / txy;
+        d.ntx_z = (g->nx + tz - 1) / tz;
+        d.xy_begin = q;
+        d.xy_count = g->nz * d.ntx_xy;
+        q += d.xy_count;
+        d.fast = (g->nx % 64 == 0 && (reinterpret_cast<uintptr_t>(maps[i].occ) & 15) == 0) ? 1 : 0;
+        d.occ = maps[i].occ;
+        d.d2 = maps[i].d2;
+        d.site = maps[i].site;
+        p.nx_max = std::max(p.nx_max, g->nx);
+        p.ny_max = std::max(p.ny_max, g->ny);
+        p.nz_max = std::max(p.nz_max, g->nz);
+    }
+    p.args.n_xy = q;
+    for (int i = 0; i < n; ++i) {
+        MapDesc& d = p.args.m[i];
+        d.z_begin = q;
+        q += d.ny * d.ntx_z;
+    }
+    p.args.n_total = q;
+    return EDT_OK;
+}
+
+std::mutex g_batch_mu;
+std::map<std::tuple<int, int, int, int>, EdtTuning> g_batch_tuned;
+
+EdtTuning batch_default(int nx, int ny, int nz)
+{
+    edt_grid_t g{nx, ny, nz, {0.0f, 0.0f, 0.0f}, 1.0f};
+    EdtTuning t = default_tuning(&g);
+    if (t.xy_tw > 32) t.xy_tw = 32;
+    if (t.z_tw < 16) t.z_tw = 16;
+    return t;
+}
+
+EdtTuning batch_current(int n, int nx, int ny, int nz)
+{
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_batch_tuned.find(std::make_tuple(n, nx, ny, nz));
+    return it != g_batch_tuned.end() ? it->second : batch_default(nx, ny, nz);
+}
+
+template <int TXY, int TZ, int NWMAX>
+int launch_batched_t(const BatchPlan& p, unsigned* ws, hipStream_t st)
+{
+    auto kern = k_edt_batched<TXY, TZ, NWMAX>;
+    const size_t lds = std::max(xy_lds(TXY, p.ny_max), z_lds(TZ, p.nz_max));
+    static bool lds_ok = false;
+    static int per_cu = 0;
+    static int n_cu = 0;
+    if (!lds_ok) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192) != hipSuccess) {
+            set_error("edt_compute_batched: hipFuncSetAttribute failed");
+            return EDT_ERR_HIP;
+        }
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            set_error("edt_compute_batched: device query failed");
+            return EDT_ERR_HIP;
+        }
+        lds_ok = true;
+    }
+    // resident work-groups for this LDS size (recomputed: it depends on the batch)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), NT,
+                                                     lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int grid = std::max(1, std::min(p.args.n_total, per_cu * n_cu));
+    const int nws = WS_DONE + p.args.n_maps;
+    hipLaunchKernelGGL(k_batch_reset, dim3((nws + 63) / 64), dim3(64), 0, st, ws, nws);
+    int rc = check_launch("k_batch_reset");
+    if (rc) return rc;
+    // about 0.5 s of 8-slot sleeps before a wait gives up
+    const unsigned spin_limit = 1u << 21;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, p.args, ws, spin_limit);
+    return check_launch("k_edt_batched");
+}
+
+template <int TXY, int TZ>
+int launch_batched_tz(const BatchPlan& p, unsigned* ws, hipStream_t st)
+{
+    return p.nx_max <= 256 ? launch_batched_t<TXY, TZ, 4>(p, ws, st)
+                           : launch_batched_t<TXY, TZ, 8>(p, ws, st);
+}
+
+int launch_batched(const BatchPlan& p, int txy, int tz, unsigned* ws, hipStream_t st)
+{
+    if (txy == 32) {
+        if (tz == 64) return launch_batched_tz<32, 64>(p, ws, st);
+        if (tz == 32) return launch_batched_tz<32, 32>(p, ws, st);
+        if (tz == 16) return launch_batched_tz<32, 16>(p, ws, st);
+    } else if (txy == 16) {
+        if (tz == 64) return launch_batched_tz<16, 64>(p, ws, st);
+        if (tz == 32) return launch_batched_tz<16, 32>(p, ws, st);
+        if (tz == 16) return launch_batched_tz<16, 16>(p, ws, st);
+    }
+    set_error("edt_compute_batched: tiles (%d, %d) not available for batches", txy, tz);
+    return EDT_ERR_UNSUPPORTED;
+}
+
+int batch_common(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t ws_bytes,
+                 const edt_tuning_t* tuning, BatchPlan& p, EdtTuning& t)
+{
+    if (!maps || n_maps < 1 || n_maps > EDT_BATCH_MAX) {
+        set_error("edt_compute_batched: need 1..%d maps, got %d", EDT_BATCH_MAX, n_maps);
+        return EDT_ERR_ARG;
+    }
+    if (!ws || ws_bytes < edt_batch_workspace_bytes(n_maps)) {
+        set_error("edt_compute_batched: workspace of %zu bytes is below %zu", ws_bytes,
+                  edt_batch_workspace_bytes(n_maps));
+        return EDT_ERR_WORKSPACE;
+    }
+    int nx = 0, ny = 0, nz = 0;
+    for (int i = 0; i < n_maps; ++i) {
+        nx = std::max(nx, maps[i].grid.nx);
+        ny = std::max(ny, maps[i].grid.ny);
+        nz = std::max(nz, maps[i].grid.nz);
+    }
+    if (tuning) {
+        t.xy_tw = tuning->xy_tile;
+        t.z_tw = tuning->z_tile;
+    } else {
+        t = batch_current(n_maps, nx, ny, nz);
+    }
+    if ((t.xy_tw != 16 && t.xy_tw != 32) || (t.z_tw != 16 && t.z_tw != 32 && t.z_tw != 64)) {
+        set_error("edt_compute_batched: tiles (%d, %d) not available for batches", t.xy_tw, t.z_tw);
+        return EDT_ERR_UNSUPPORTED;
+    }
+    int rc = make_plan(maps, n_maps, t.xy_tw, t.z_tw, p);
+    if (rc) return rc;
+    constexpr size_t LDS_MAX = 160 * 1024 - 8192;
+    if (xy_lds(t.xy_tw, p.ny_max) > LDS_MAX || z_lds(t.z_tw, p.nz_max) > LDS_MAX) {
+        set_error("edt_compute_batched: tiles (%d, %d) need too much local memory", t.xy_tw, t.z_tw);
+        return EDT_ERR_UNSUPPORTED;
+    }
+    return EDT_OK;
+}
+
+}  // namespace
+
+}  // namespace edtmi
+
+using namespace edtmi;
+
+extern "C" {
+
+size_t edt_batch_workspace_bytes(int32_t n_maps)
+{
+    if (n_maps < 0) n_maps = 0;
+    const size_t words = WS_DONE + (size_t)n_maps;
+    return (words * 4 + 255) / 256 * 256;
+}
+
+int edt_compute_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t ws_bytes,
+                        const edt_tuning_t* tuning, void* stream)
+{
+    BatchPlan p;
+    EdtTuning t;
+    int rc = batch_common(maps, n_maps, ws, ws_bytes, tuning, p, t);
+    if (rc) return rc;
+    return launch_batched(p, t.xy_tw, t.z_tw, static_cast<unsigned*>(ws), as_stream(stream));
+}
+
+int edt_batch_status(const void* ws, int32_t* timed_out, void* stream)
+{
+    if (!ws || !timed_out) {
+        set_error("edt_batch_status: NULL argument");
+        return EDT_ERR_ARG;
+    }
+    unsigned flag = 0;
+    const hipStream_t st = as_stream(stream);
+    if (hipMemcpyAsync(&flag, static_cast<const unsigned*>(ws) + WS_ERR, sizeof(flag),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("edt_batch_status: copy failed");
+        return EDT_ERR_HIP;
+    }
+    *timed_out = flag ? 1 : 0;
+    return EDT_OK;
+}
+
+int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t ws_bytes,
+                         int32_t reps, edt_tuning_t* best, float* best_us, void* stream)
+{
+    if (reps < 1) {
+        set_error("edt_autotune_batched: reps < 1");
+        return EDT_ERR_ARG;
+    }
+    const hipStream_t st = as_stream(stream);
+    const int XY[] = {16, 32};
+    const int Z[] = {16, 32, 64};
+    float best_ms = 1e30f;
+    EdtTuning bt{0, 0};
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        set_error("edt_autotune_batched: hipEventCreate failed");
+        return EDT_ERR_HIP;
+    }
+    int rc = EDT_OK;
+    for (int txy : XY) {
+        for (int tz : Z) {
+            edt_tuning_t cand{txy, tz};
+            BatchPlan p;
+            EdtTuning t;
+            rc = batch_common(maps, n_maps, ws, ws_bytes, &cand, p, t);
+            if (rc == EDT_ERR_UNSUPPORTED) {
+                rc = EDT_OK;
+                continue;
+            }
+            if (rc) break;
+            float total = 0.0f;
+            for (int r = 0; r <= reps && !rc; ++r) {
+                (void)hipEventRecord(a, st);
+                rc = launch_batched(p, txy, tz, static_cast<unsigned*>(ws), st);
+                (void)hipEventRecord(b, st);
+                if (rc) break;
+                if (hipEventSynchronize(b) != hipSuccess) {
+                    set_error("edt_autotune_batched: hipEventSynchronize failed");
+                    rc = EDT_ERR_HIP;
+                    break;
+                }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (r > 0) total += ms;   // run 0 is a warm-up
+            }
+            if (rc) break;
+            if (total / reps < best_ms) {
+                best_ms = total / reps;
+                bt = EdtTuning{txy, tz};
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if (!bt.xy_tw) {
+        set_error("edt_autotune_batched: no tile pair fits this batch");
+        return EDT_ERR_UNSUPPORTED;
+    }
+    int nx = 0, ny = 0, nz = 0;
+    for (int i = 0; i < n_maps; ++i) {
+        nx = std::max(nx, maps[i].grid.nx);
+        ny = std::max(ny, maps[i].grid.ny);
+        nz = std::max(nz, maps[i].grid.nz);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        g_batch_tuned[std::make_tuple(n_maps, nx, ny, nz)] = bt;
+    }
+    if (best) {
+        best->xy_tile = bt.xy_tw;
+        best->z_tile = bt.z_tw;
+    }
+    if (best_us) *best_us = 1000.0f * best_ms;
+    // leave the chosen tiling's result in the outputs
+    BatchPlan p;
+    EdtTuning t;
+    edt_tuning_t chosen{bt.xy_tw, bt.z_tw};
+    rc = batch_common(maps, n_maps, ws, ws_bytes, &chosen, p, t);
+    if (!rc) rc = launch_batched(p, bt.xy_tw, bt.z_tw, static_cast<unsigned*>(ws), st);
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) {
+        set_error("edt_autotune_batched: stream synchronisation failed");
+        rc = EDT_ERR_HIP;
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,669 @@
+#pragma once
+// Device code of the exact squared EDT tiles, shared by the per-map kernels
+// (edt_core.hip) and the persistent batched kernel (batch.hip).
+//
+// The transform is separable (Sec. III-C, Alg. 1).  Step 1 finds the nearest
+// site within each row; step 2 keeps, per column, the proximate sites (those
+// whose distance function reaches the lower envelope of all of them); step 3
+// reads every position of the column off that envelope; step 4 repeats
+// steps 2-3 along z over the 2D results.  Every step keeps the smaller
+// coordinate on equal distance, so with the passes in x, y, z order the site
+// is the smallest linear index among the equidistant occupied voxels.
+//
+// Envelope arithmetic.  A site at position p with accumulated squared
+// distance h contributes f(q) = h + (q - p)^2 = K - 2qp + q^2, K = h + p^2.
+// The middle one of three sites a < b < c is dominated -- owns no stretch of
+// the line -- iff (K_c - K_b)(b - a) <= (K_b - K_a)(c - b); a query moves to
+// the next proximate site only while that one is strictly closer.
+//
+// Banding (the m2 / m3 bands of the paper's steps 2 and 3).  Each column is
+// cut into NB bands; one thread per (column, band) builds the band's own
+// envelope with a stack.  The band envelopes of a column are then merged in
+// log2(NB) rounds of independent pairwise merges: the envelope of two
+// neighbouring groups keeps a prefix of the left one and a suffix of the
+// right one, found by popping dominated sites on either side of the seam
+// until neither side pops.  Each (column, band) thread then locates the
+// envelope site of its first position (walking from its own band's range,
+// then a binary search) and marches through its positions with a
+// strength-reduced test.  The stacks keep packed self-contained entries
+// (position | x' << 10 [| y' << 20]), so a key is recomputed from an entry
+// and no side table is needed.
+//
+//   xy tile   work-group = (z slice, TW consecutive columns).  Each wave
+//             reduces whole rows to a 64-bit ballot word for the tile plus
+//             the nearest set bit left and right of it; the (column, band)
+//             threads derive x' per row from those and feed their stacks.
+//             Output: the 2D site x' | y' << 16 of every voxel, written into
+//             the site buffer (0xFFFFFFFF if the slice is empty).
+//   z tile    work-group = (row y, TW consecutive columns), all z.  Threads
+//             load their band of the packed 2D sites (coalesced along x),
+//             build, merge, query and overwrite d2 and site in place: every
+//             read of a column happens before the first barrier and every
+//             write after the last, and a column belongs to one work-group.
+#include "common.h"
+
+
+namespace edtmi {
+namespace tiles {
+
+constexpr int NT = 256;                 // threads per work-group
+constexpr uint32_t XY_NONE = 0xFFFFFFFFu;
+constexpr uint32_t POS_MASK = 1023u;
+
+// 24-bit multiply (full rate on CDNA; v_mul_lo_u32 is quarter rate): exact
+// when both operands fit in 24 signed bits and the product in 32.
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+
+// Keys are below 3 * 1023^2 < 2^22 and position gaps below 2^10, so every
+// operand fits in 24 bits; with all axes <= 512 the products stay below 2^31.
+template <bool WIDE>
+__device__ __forceinline__ bool dominated(int pa, int ka, int pb, int kb, int pc, int kc)
+{
+    if constexpr (WIDE) {
+        return (int64_t)(kc - kb) * (pb - pa) <= (int64_t)(kb - ka) * (pc - pb);
+    } else {
+        return mul24(kc - kb, pb - pa) <= mul24(kb - ka, pc - pb);
+    }
+}
+
+// f_1(q) < f_0(q); both sides carry the same q^2, and every term stays below
+// 2^31 for positions and keys of grids up to 1024 per axis.
+__device__ __forceinline__ bool next_closer(int p0, int k0, int p1, int k1, int q)
+{
+    return k1 - 2 * mul24(q, p1) < k0 - 2 * mul24(q, p0);
+}
+
+// entry of the y pass: y' | x' << 10
+struct KeyY {
+    int xc;
+    __device__ __forceinline__ int operator()(uint32_t e) const
+    {
+        const int p = (int)(e & POS_MASK);
+        const int d = xc - (int)(e >> 10);
+        return mul24(d, d) + mul24(p, p);
+    }
+};
+
+// entry of the z pass: z' | x' << 10 | y' << 20
+struct KeyZ {
+    int xc, yc;
+    __device__ __forceinline__ int operator()(uint32_t e) const
+    {
+        const int p = (int)(e & POS_MASK);
+        const int dx = xc - (int)((e >> 10) & POS_MASK);
+        const int dy = yc - (int)(e >> 20);
+        return mul24(dx, dx) + mul24(dy, dy) + mul24(p, p);
+    }
+};
+
+// Band-local envelope of sites pushed in increasing position; the two
+// topmost entries stay in registers.
+template <int TW, bool WIDE, class KeyF>
+struct BandStack {
+    uint32_t* slot;   // this thread's slots, stride TW
+    int top;
+    int pa, ka, pb, kb;
+
+    __device__ __forceinline__ void push(uint32_t e, int p, int k, const KeyF& key)
+    {
+        while (top >= 2 && dominated<WIDE>(pa, ka, pb, kb, p, k)) {
+            --top;
+            pb = pa;
+            kb = ka;
+            if (top >= 2) {
+                const uint32_t ea = slot[(top - 2) * TW];
+                pa = (int)(ea & POS_MASK);
+                ka = key(ea);
+            }
+        }
+        slot[top * TW] = e;
+        ++top;
+        pa = pb;
+        ka = kb;
+        pb = p;
+        kb = k;
+    }
+};
+
+// Per-column band bookkeeping in LDS, [NB][TW] each: the surviving range
+// [lo, hi) of every band's stack and the next band with a non-empty range.
+struct BandMeta {
+    int16_t* lo;
+    int16_t* hi;
+    int16_t* nxt;     // next band with a non-empty range (NB if none)
+    int16_t* prv;     // previous band with a non-empty range (-1 if none)
+};
+
+// Merge the envelope of bands [gl, gm) (already merged) with that of bands
+// [gm, gr): the result keeps a prefix of the left chain and a suffix of the
+// right one, found by popping the seam's dominated sites on either side
+// until neither side pops.  s, t are the left chain's last two sites, c, d
+// the right chain's first two; all four stay in registers.  Only this
+// thread touches bands [gl, gr) meanwhile.
+template <int TW, bool WIDE, class KeyF>
+__device__ void merge_group(const uint32_t* ent, int L, int col, const BandMeta& m, const KeyF& key,
+                            int gl, int gm, int gr)
+{
+    auto E = [&](int b, int i) { return ent[(b * L + i) * TW + col]; };
+    auto LO = [&](int b) -> int16_t& { return m.lo[b * TW + col]; };
+    auto HI = [&](int b) -> int16_t& { return m.hi[b * TW + col]; };
+    int lastL = gm - 1;
+    while (lastL >= gl && LO(lastL) == HI(lastL)) --lastL;
+    if (lastL < gl) return;
+    int firstR = gm;
+    while (firstR < gr && LO(firstR) == HI(firstR)) ++firstR;
+    if (firstR >= gr) return;
+    int cntL = 0, cntR = 0;
+    for (int b = gl; b < gm; ++b) cntL += HI(b) - LO(b);
+    for (int b = gm; b < gr; ++b) cntR += HI(b) - LO(b);
+    int loL = LO(lastL), hiL = HI(lastL), loR = LO(firstR), hiR = HI(firstR);
+    // neighbouring non-empty bands inside the group (they exist when asked)
+    auto prevL = [&](int b) {
+        int p = b - 1;
+        while (p > gl && LO(p) == HI(p)) --p;
+        return p;
+    };
+    auto nextR = [&](int b) {
+        int x = b + 1;
+        while (x < gr - 1 && LO(x) == HI(x)) ++x;
+        return x;
+    };
+    auto secondL = [&]() {
+        if (hiL - loL >= 2) return E(lastL, hiL - 2);
+        const int p = prevL(lastL);
+        return E(p, HI(p) - 1);
+    };
+    auto secondR = [&]() {
+        if (hiR - loR >= 2) return E(firstR, loR + 1);
+        const int x = nextR(firstR);
+        return E(x, LO(x));
+    };
+    uint32_t e = E(lastL, hiL - 1);
+    int pt = (int)(e & POS_MASK), kt = key(e);
+    int ps = 0, ks = 0;
+    if (cntL >= 2) {
+        e = secondL();
+        ps = (int)(e & POS_MASK);
+        ks = key(e);
+    }
+    e = E(firstR, loR);
+    int pc = (int)(e & POS_MASK), kc = key(e);
+    int pd = 0, kd = 0;
+    if (cntR >= 2) {
+        e = secondR();
+        pd = (int)(e & POS_MASK);
+        kd = key(e);
+    }
+    for (;;) {
+        if (cntL >= 2 && dominated<WIDE>(ps, ks, pt, kt, pc, kc)) {
+            --hiL;
+            --cntL;
+            if (hiL == loL) {
+                HI(lastL) = (int16_t)hiL;
+                lastL = prevL(lastL);
+                loL = LO(lastL);
+                hiL = HI(lastL);
+            }
+            pt = ps;
+            kt = ks;
+            if (cntL >= 2) {
+                e = secondL();
+                ps = (int)(e & POS_MASK);
+                ks = key(e);
+            }
+            continue;
+        }
+        if (cntR >= 2 && dominated<WIDE>(pt, kt, pc, kc, pd, kd)) {
+            ++loR;
+            --cntR;
+            if (loR == hiR) {
+                LO(firstR) = (int16_t)loR;
+                firstR = nextR(firstR);
+                loR = LO(firstR);
+                hiR = HI(firstR);
+            }
+            pc = pd;
+            kc = kd;
+            if (cntR >= 2) {
+                e = secondR();
+                pd = (int)(e & POS_MASK);
+                kd = key(e);
+            }
+            continue;
+        }
+        break;
+    }
+    HI(lastL) = (int16_t)hiL;
+    LO(firstR) = (int16_t)loR;
+}
+
+// Links between the non-empty band ranges of one column.
+template <int TW, int NB>
+__device__ void link_bands(int col, const BandMeta& m)
+{
+    int nxt = NB;
+    for (int b = NB - 1; b >= 0; --b) {
+        m.nxt[b * TW + col] = (int16_t)nxt;
+        if (m.lo[b * TW + col] < m.hi[b * TW + col]) nxt = b;
+    }
+    int prv = -1;
+    for (int b = 0; b < NB; ++b) {
+        m.prv[b * TW + col] = (int16_t)prv;
+        if (m.lo[b * TW + col] < m.hi[b * TW + col]) prv = b;
+    }
+}
+
+// All bands of every column of the tile: log2(NB) rounds of pairwise group
+// merges (groups of one round are independent), then the band links.
+template <int TW, int NB, bool WIDE, class KeyF>
+__device__ __forceinline__ void merge_all(const uint32_t* ent, int L, int col, int band, bool live,
+                                          const BandMeta& m, const KeyF& key)
+{
+    for (int half = 1; half < NB; half <<= 1) {
+        const int span = half << 1;
+        if (live && (band & (span - 1)) == 0)
+            merge_group<TW, WIDE>(ent, L, col, m, key, band, band + half, band + span);
+        __syncthreads();
+    }
+    if (live && band == col * NB / TW) link_bands<TW, NB>(col, m);
+    __syncthreads();
+}
+
+// Positions [q0, q1) of one column off the merged envelope.  The site of
+// q0 is found first (scan over band ranges, binary search inside one); then
+// the march moves to the next envelope site while it is strictly closer:
+// with dK = K1 - K0 and dp2 = 2 (p1 - p0) > 0 that is dK < q * dp2, kept as
+// a running difference.  begin(q, entry, pos, key) is called whenever the
+// site changes (and at q0), step(q) once per position; none(q0, q1) if the
+// column has no site.
+template <int TW, int NB, class KeyF, class Begin, class Step, class None>
+__device__ __forceinline__ void query_band(const uint32_t* ent, int L, int col, const BandMeta& m,
+                                           int q0, int q1, const KeyF& key, Begin begin, Step step,
+                                           None none)
+{
+    auto E = [&](int b, int i) { return ent[(b * L + i) * TW + col]; };
+    auto LO = [&](int b) -> int { return m.lo[b * TW + col]; };
+    auto HI = [&](int b) -> int { return m.hi[b * TW + col]; };
+    auto NX = [&](int b) -> int { return m.nxt[b * TW + col]; };
+    auto PV = [&](int b) -> int { return m.prv[b * TW + col]; };
+    // start from the nearest non-empty band to this one and walk to the band
+    // range holding the envelope site of q0
+    const int own = q0 / L;
+    int j;
+    if (LO(own) < HI(own)) j = own;
+    else if (NX(own) < NB) j = NX(own);
+    else if (PV(own) >= 0) j = PV(own);
+    else {
+        none(q0, q1);
+        return;
+    }
+    int k;
+    for (;;) {
+        const int hij = HI(j);
+        const int jn = NX(j);
+        if (jn < NB) {
+            const uint32_t el = E(j, hij - 1), en = E(jn, LO(jn));
+            if (next_closer((int)(el & POS_MASK), key(el), (int)(en & POS_MASK), key(en), q0)) {
+                j = jn;
+                continue;
+            }
+        }
+        const int jp = PV(j);
+        if (jp >= 0) {
+            const uint32_t el = E(jp, HI(jp) - 1), ef = E(j, LO(j));
+            if (!next_closer((int)(el & POS_MASK), key(el), (int)(ef & POS_MASK), key(ef), q0)) {
+                j = jp;
+                continue;
+            }
+        }
+        int a = LO(j), b = hij - 1;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            const uint32_t e0 = E(j, mid), e1 = E(j, mid + 1);
+            if (next_closer((int)(e0 & POS_MASK), key(e0), (int)(e1 & POS_MASK), key(e1), q0))
+                a = mid + 1;
+            else
+                b = mid;
+        }
+        k = a;
+        break;
+    }
+    uint32_t ek = E(j, k);
+    int pk = (int)(ek & POS_MASK), kk = key(ek);
+    int hij = HI(j);
+    // next site and the running test value g(q) = q * dp2 - dK (advance iff g > 0)
+    int jn = 0, kn = 0, pn = 0, kkn = 0, dp2 = 0, g = 0;
+    uint32_t en = 0;
+    bool has_next = false;
+    auto load_next = [&](int q) {
+        if (k + 1 < hij) {
+            jn = j;
+            kn = k + 1;
+        } else {
+            jn = NX(j);
+            kn = jn < NB ? LO(jn) : 0;
+        }
+        has_next = jn < NB;
+        if (has_next) {
+            en = E(jn, kn);
+            pn = (int)(en & POS_MASK);
+            kkn = key(en);
+            dp2 = 2 * (pn - pk);
+            g = mul24(q, dp2) - (kkn - kk);
+        }
+    };
+    load_next(q0);
+    begin(q0, ek, pk, kk);
+    for (int q = q0; q < q1; ++q) {
+        if (has_next && g > 0) {
+            do {
+                if (jn != j) hij = HI(jn);
+                j = jn;
+                k = kn;
+                ek = en;
+                pk = pn;
+                kk = kkn;
+                load_next(q);
+            } while (has_next && g > 0);
+            begin(q, ek, pk, kk);
+        }
+        step(q);
+        g += dp2;
+    }
+}
+
+// bit i set iff byte i of w is nonzero
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t w)
+{
+    uint32_t t = w | (w >> 4);
+    t |= t >> 2;
+    t |= t >> 1;
+    t &= 0x01010101u;
+    return (t * 0x01020408u) >> 24;
+}
+
+// ---------------------------------------------------------------------------
+// steps 1-3 per (slice, column tile)
+// ---------------------------------------------------------------------------
+// Words of the 16-byte row path's staging buffer in LDS (8 KiB).
+constexpr int XSTAGE_WORDS = 1024;
+
+// Dynamic LDS of k_edt_xy: envelope entries (or the row staging buffer,
+// whichever is larger) plus three row-record arrays.
+__host__ __device__ inline size_t z_lds(int tw, int nzv)
+{
+    return (size_t)4 * NT * ((nzv + NT / tw - 1) / (NT / tw));
+}
+
+__host__ __device__ inline size_t xy_lds(int tw, int nyv)
+{
+    const size_t ent = (size_t)4 * NT * ((nyv + NT / tw - 1) / (NT / tw));
+    return (ent > 8 * (size_t)XSTAGE_WORDS ? ent : 8 * (size_t)XSTAGE_WORDS) + 12 * (size_t)nyv;
+}
+
+// One xy tile: slice z, columns [x0, x0 + TW), T = z * ntx + x0 / TW.
+template <int TW, bool WIDE, int NWMAX, bool FAST>
+__device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
+                                            uint32_t* __restrict__ xy, int nx, int ny, int nz,
+                                            int ntx, int T, uint32_t* lds)
+{
+    constexpr int NB = NT / TW;
+    constexpr int RB = 32 / NWMAX > 0 ? 32 / NWMAX : 1;   // rows in flight per wave (32 byte loads)
+    constexpr int XCH = 8;                                 // 16-byte loads in flight per thread
+    (void)nz;
+    const int L = (ny + NB - 1) / NB;
+    // the 16-byte row path stages rows in the envelope area, which is only
+    // written after step 1
+    const int ent_words = max(NB * L * TW, 2 * XSTAGE_WORDS);
+    uint32_t* ent = lds;                                                // [NB*L][TW]
+    uint64_t* stage = reinterpret_cast<uint64_t*>(lds);                 // [XSTAGE_WORDS]
+    uint64_t* rword = reinterpret_cast<uint64_t*>(lds + ent_words);     // [ny]
+    int16_t* rleft = reinterpret_cast<int16_t*>(rword + ny);            // [ny]
+    int16_t* rright = rleft + ny;                                       // [ny]
+    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_prv[NB * TW];
+    const BandMeta meta{s_lo, s_hi, s_nxt, s_prv};
+
+    const int z = T / ntx;
+    const int x0 = (T - z * ntx) * TW;
+    const int w0 = x0 >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwords = (nx + 63) >> 6;
+
+    // ---- step 1: per row, the tile's 64-bit occupancy word and the nearest
+    // occupied voxel left and right of the word
+    if constexpr (FAST) {
+        // nx % 64 == 0 and 16-byte aligned rows: blocks of rows arrive as
+        // 16-byte loads, become 16-bit masks in LDS (whole 64-bit words per
+        // row), and one thread per row derives the row record from them
+        const int nw = nx >> 6;
+        const int rblk = min(ny, XSTAGE_WORDS / nw);
+        uint16_t* stage16 = reinterpret_cast<uint16_t*>(stage);
+        for (int y0 = 0; y0 < ny; y0 += rblk) {
+            const int rows = min(rblk, ny - y0);
+            const int nch = rows * (nx >> 4);
+            const uint4* src = reinterpret_cast<const uint4*>(occ + ((size_t)z * ny + y0) * nx);
+            for (int i0 = 0; i0 < nch; i0 += NT * XCH) {
+                uint4 v[XCH];
+#pragma unroll
+                for (int u = 0; u < XCH; ++u) v[u] = src[min(i0 + u * NT + (int)threadIdx.x, nch - 1)];
+#pragma unroll
+                for (int u = 0; u < XCH; ++u) {
+                    const int i = i0 + u * NT + (int)threadIdx.x;
+                    if (i < nch)
+                        stage16[i] = (uint16_t)(nonzero_bytes(v[u].x) | (nonzero_bytes(v[u].y) << 4) |
+                                                (nonzero_bytes(v[u].z) << 8) | (nonzero_bytes(v[u].w) << 12));
+                }
+            }
+            __syncthreads();
+            for (int r = threadIdx.x; r < rows; r += NT) {
+                const uint64_t* w = stage + r * nw;
+                int left = -1, right = -1;
+                for (int c = w0 - 1; c >= 0; --c)
+                    if (w[c]) {
+                        left = c * 64 + 63 - __clzll(w[c]);
+                        break;
+                    }
+                for (int c = w0 + 1; c < nw; ++c)
+                    if (w[c]) {
+                        right = c * 64 + __ffsll((unsigned long long)w[c]) - 1;
+                        break;
+                    }
+                rword[y0 + r] = w[w0];
+                rleft[y0 + r] = (int16_t)left;
+                rright[y0 + r] = (int16_t)right;
+            }
+            __syncthreads();
+        }
+    } else
+    for (int yb = wave; yb < ny; yb += (NT / 64) * RB) {
+        // unconditional loads from clamped (in-bounds) addresses so that all
+        // RB * NWMAX of them are in flight before the first use; lanes past
+        // the row end are masked afterwards
+        uint8_t b[RB][NWMAX];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int y = min(yb + r * (NT / 64), ny - 1);
+            const uint8_t* row = occ + ((size_t)z * ny + y) * nx;
+#pragma unroll
+            for (int c = 0; c < NWMAX; ++c)
+                b[r][c] = row[min(c * 64 + lane, nx - 1)];
+        }
+#pragma unroll
+        for (int c = 0; c < NWMAX; ++c)
+            if (c * 64 + lane >= nx) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r) b[r][c] = 0;
+            }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int y = yb + r * (NT / 64);
+            if (y >= ny) break;
+            uint64_t mine = 0;
+            int left = -1, right = -1;
+#pragma unroll
+            for (int c = 0; c < NWMAX; ++c) {
+                if (c < nwords) {
+                    const uint64_t mk = __ballot(b[r][c] != 0);
+                    if (c < w0) {
+                        if (mk) left = c * 64 + 63 - __clzll(mk);
+                    } else if (c == w0) {
+                        mine = mk;
+                    } else if (mk && right < 0) {
+                        right = c * 64 + __ffsll((unsigned long long)mk) - 1;
+                    }
+                }
+            }
+            if (lane == 0) {
+                rword[y] = mine;
+                rleft[y] = (int16_t)left;
+                rright[y] = (int16_t)right;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- step 2, band-local: x' per row from the row records, then push
+    const int col = threadIdx.x % TW;
+    const int band = threadIdx.x / TW;
+    const int xc = x0 + col;
+    const bool live = xc < nx;
+    const KeyY key{xc};
+    const int q0 = band * L;
+    const int q1 = min(ny, q0 + L);
+    {
+        const int bit = (x0 & 63) + col;
+        const uint64_t lmask = (2ull << bit) - 1ull;
+        const uint64_t rmask = ~0ull << bit;
+        BandStack<TW, WIDE, KeyY> st{ent + q0 * TW + col, 0, 0, 0, 0, 0};
+        if (live) {
+            for (int y = q0; y < q1; ++y) {
+                const uint64_t mk = rword[y];
+                const uint64_t lm = mk & lmask, rm = mk & rmask;
+                const int xl = lm ? (w0 * 64 + 63 - __clzll(lm)) : (int)rleft[y];
+                const int xr = rm ? (w0 * 64 + __ffsll((unsigned long long)rm) - 1) : (int)rright[y];
+                int xp;
+                if (xl < 0) xp = xr;
+                else if (xr < 0) xp = xl;
+                else xp = (xc - xl <= xr - xc) ? xl : xr;
+                if (xp < 0) continue;
+                const int d = xc - xp;
+                st.push((uint32_t)y | ((uint32_t)xp << 10), y, mul24(d, d) + mul24(y, y), key);
+            }
+        }
+        s_lo[band * TW + col] = 0;
+        s_hi[band * TW + col] = (int16_t)st.top;
+    }
+    __syncthreads();
+    merge_all<TW, NB, WIDE>(ent, L, col, band, live, meta, key);
+
+    // ---- step 3: every row of the band
+    if (!live || q0 >= q1) return;
+    uint32_t* out = xy + (size_t)z * ny * nx + (size_t)q0 * nx + xc;
+    uint32_t val = 0;
+    query_band<TW, NB>(
+        ent, L, col, meta, q0, q1, key,
+        [&](int, uint32_t e, int, int) { val = (e >> 10) | ((e & POS_MASK) << 16); },
+        [&](int) {
+            *out = val;
+            out += nx;
+        },
+        [&](int a, int b) {
+            for (int q = a; q < b; ++q, out += nx) *out = XY_NONE;
+        });
+}
+
+// ---------------------------------------------------------------------------
+// step 4 per (row, column tile)
+// ---------------------------------------------------------------------------
+// One z tile: row y, columns [x0, x0 + TW), all z; T = y * ntx + x0 / TW.
+template <int TW, bool WIDE>
+__device__ __forceinline__ void edt_z_tile(int32_t* d2, int32_t* site, int nx, int ny, int nz,
+                                           int ntx, int T, uint32_t* lds)
+{
+    constexpr int NB = NT / TW;
+    constexpr int CH = 8;   // positions per software-pipelined chunk
+    const int L = (nz + NB - 1) / NB;
+    uint32_t* ent = lds;    // [NB*L][TW]
+    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_prv[NB * TW];
+    const BandMeta meta{s_lo, s_hi, s_nxt, s_prv};
+
+    const int y = T / ntx;
+    const int x0 = (T - y * ntx) * TW;
+    const int col = threadIdx.x % TW;
+    const int band = threadIdx.x / TW;
+    const int xc = x0 + col;
+    const bool live = xc < nx;
+    const KeyZ key{xc, y};
+    const size_t plane = (size_t)nx * ny;
+    const unsigned plane32 = (unsigned)nx * (unsigned)ny;
+    const size_t base = (size_t)y * nx + xc;
+    const int q0 = band * L;
+    const int q1 = min(nz, q0 + L);
+
+    {
+        BandStack<TW, WIDE, KeyZ> st{ent + q0 * TW + col, 0, 0, 0, 0, 0};
+        if (live && q0 < q1) {
+            // chunks of CH positions, software-pipelined: the next chunk's
+            // loads (clamped into the band) are in flight while this chunk is
+            // pushed, with the chunk loop fully unrolled
+            auto load = [&](uint32_t (&v)[CH], int zb) {
+#pragma unroll
+                for (int i = 0; i < CH; ++i)   // z * plane < 2^32 with z < 2^10, plane <= 2^20
+                    v[i] = (uint32_t)site[base + __umul24((unsigned)min(zb + i, q1 - 1), plane32)];
+            };
+            uint32_t cur[CH], nxt[CH];
+            load(cur, q0);
+            for (int zb = q0; zb < q1; zb += CH) {
+                load(nxt, zb + CH);
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const int zz = zb + i;
+                    if (zz < q1 && cur[i] != XY_NONE) {
+                        const int xp = (int)(cur[i] & 0xFFFFu), yp = (int)(cur[i] >> 16);
+                        const int dx = xc - xp, dy = y - yp;
+                        st.push((uint32_t)zz | ((uint32_t)xp << 10) | ((uint32_t)yp << 20), zz,
+                                mul24(dx, dx) + mul24(dy, dy) + mul24(zz, zz), key);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < CH; ++i) cur[i] = nxt[i];
+            }
+        }
+        s_lo[band * TW + col] = 0;
+        s_hi[band * TW + col] = (int16_t)st.top;
+    }
+    __syncthreads();
+    merge_all<TW, NB, WIDE>(ent, L, col, band, live, meta, key);
+
+    if (!live || q0 >= q1) return;
+    int dd = 0, inc = 0;
+    int32_t ss = 0;
+    int32_t* od = d2 + base + (size_t)q0 * plane;
+    int32_t* os = site + base + (size_t)q0 * plane;
+    query_band<TW, NB>(
+        ent, L, col, meta, q0, q1, key,
+        [&](int q, uint32_t e, int p, int k) {
+            // along a run of one site, (q - p)^2 + h grows by 2(q - p) + 1
+            dd = k - 2 * mul24(q, p) + mul24(q, q);
+            inc = 2 * (q - p) + 1;
+            ss = (int32_t)(((e >> 10) & POS_MASK) + (uint32_t)nx * ((e >> 20) + (uint32_t)ny * (uint32_t)p));
+        },
+        [&](int) {
+            *od = dd;
+            *os = ss;
+            od += plane;
+            os += plane;
+            dd += inc;
+            inc += 2;
+        },
+        [&](int a, int b) {
+            for (int q = a; q < b; ++q) {
+                d2[base + (size_t)q * plane] = 0x7FFFFFFF;
+                site[base + (size_t)q * plane] = -1;
+            }
+        });
+}
+
+}  // namespace tiles
+}  // namespace edtmi

@@ -44,13 +44,21 @@ class Tuning(ctypes.Structure):
     _fields_ = [("xy_tile", ctypes.c_int32), ("z_tile", ctypes.c_int32)]
 
 
+class BatchMap(ctypes.Structure):
+    _fields_ = [("grid", EdtGrid), ("occ", ctypes.c_void_p), ("d2", ctypes.c_void_p),
+                ("site", ctypes.c_void_p)]
+
+
 SPHERE_RESULT_BYTES = ctypes.sizeof(SphereResult)   # 64
 SPHERE_RESULT_WORDS = SPHERE_RESULT_BYTES // 4
 
 EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_insert_points", "edt_insert_links", "edt_workspace_bytes", "edt_compute",
             "edt_query_spheres", "edt_compute_stage", "edt_default_tuning", "edt_compute_tuned",
-            "edt_autotune"]
+            "edt_autotune", "edt_batch_workspace_bytes", "edt_compute_batched", "edt_batch_status",
+            "edt_autotune_batched"]
+
+BATCH_MAX = 48
 
 STAGE_XY, STAGE_Z, STAGE_ALL = 1, 2, 3
 
@@ -81,6 +89,11 @@ def lib():
         "edt_compute_tuned": ([G, P, P, P, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_autotune": ([G, P, P, P, i32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float), P],
                          ctypes.c_int),
+        "edt_batch_workspace_bytes": ([i32], ctypes.c_size_t),
+        "edt_compute_batched": ([P, i32, P, ctypes.c_size_t, ctypes.POINTER(Tuning), P], ctypes.c_int),
+        "edt_batch_status": ([P, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
+        "edt_autotune_batched": ([P, i32, P, ctypes.c_size_t, i32, ctypes.POINTER(Tuning),
+                                  ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -240,3 +253,50 @@ def edt_query_spheres(grid, d2, site, centres, radii, out, stream=None):
 
 def new_query_out(m: int, device="cuda") -> torch.Tensor:
     return torch.empty((m, SPHERE_RESULT_WORDS), dtype=torch.int32, device=device)
+
+
+def batch_maps(grids, occs, d2s, sites):
+    """Host array of BatchMap descriptors for device tensors (kept alive by
+    the caller)."""
+    n = len(grids)
+    arr = (BatchMap * n)()
+    for i in range(n):
+        g = make_grid(grids[i])
+        arr[i] = BatchMap(g, _dev(occs[i], torch.uint8, "occ", _n(g)).value,
+                          _dev(d2s[i], torch.int32, "d2", _n(g)).value,
+                          _dev(sites[i], torch.int32, "site", _n(g)).value)
+    return arr
+
+
+def edt_batch_workspace_bytes(n_maps: int) -> int:
+    return int(lib().edt_batch_workspace_bytes(int(n_maps)))
+
+
+def new_batch_workspace(n_maps: int, device="cuda"):
+    return torch.empty(edt_batch_workspace_bytes(n_maps), dtype=torch.uint8, device=device)
+
+
+def edt_compute_batched(maps, ws, tuning=None, stream=None):
+    """maps: result of batch_maps(); ws: uint8 device tensor."""
+    _check(lib().edt_compute_batched(ctypes.cast(maps, ctypes.c_void_p), len(maps),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tuning(tuning),
+                                     _stream(stream)),
+           "edt_compute_batched")
+
+
+def edt_batch_status(ws, stream=None) -> bool:
+    """True if the last batch launch on ws gave up waiting (never expected)."""
+    flag = ctypes.c_int32()
+    _check(lib().edt_batch_status(ctypes.c_void_p(ws.data_ptr()), ctypes.byref(flag),
+                                  _stream(stream)), "edt_batch_status")
+    return bool(flag.value)
+
+
+def edt_autotune_batched(maps, ws, reps: int = 5, stream=None):
+    t = Tuning()
+    us = ctypes.c_float()
+    _check(lib().edt_autotune_batched(ctypes.cast(maps, ctypes.c_void_p), len(maps),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(reps),
+                                      ctypes.byref(t), ctypes.byref(us), _stream(stream)),
+           "edt_autotune_batched")
+    return (t.xy_tile, t.z_tile), float(us.value)

@@ -208,8 +208,9 @@ class Scene:
 def make_scene(grid: Grid, seed: int) -> Scene:
     g = rng(seed)
     ext = np.array(grid.extent)
-    lo = np.array(grid.origin) + np.array([0.2, 0.4, 0.1])
-    hi = np.array(grid.origin) + ext - np.array([0.2, 0.3, 0.1])
+    # workspace: the map minus margins proportional to its extent
+    lo = np.array(grid.origin) + ext * np.array([0.08, 0.16, 0.08])
+    hi = np.array(grid.origin) + ext * np.array([0.92, 0.88, 0.92])
     boxes = []
     for _ in range(5):
         side = g.uniform(0.05, 0.30, size=3)
@@ -220,7 +221,8 @@ def make_scene(grid: Grid, seed: int) -> Scene:
         spheres.append((g.uniform(lo, hi), g.uniform(0.05, 0.15)))
     d = g.normal(size=3)
     d /= np.linalg.norm(d)
-    mover = (g.uniform(lo + 0.1, hi - 0.1), 1.5 * d, 0.10)
+    r_mov = min(0.10, 0.25 * float(np.min(hi - lo)))
+    mover = (g.uniform(lo + r_mov, hi - r_mov), 1.5 * d, r_mov)
     return Scene(boxes, spheres, mover, floor_z=grid.origin[2] + 0.05,
                  wall_y=grid.origin[1] + ext[1] - 0.06, lo=lo, hi=hi)
 
@@ -451,3 +453,62 @@ def cycle_inputs(seed: int = 0, n_frames: int = 4, n_states: int = 16,
     li, cs, rs = sphere_set(robot, range(1, 8), 20)
     return CycleInputs(grid, frames, cam.T_map_cam(), lp, lo, robot, li, cs,
                        rs.astype(np.float32), random_joint_states(n_states, seed + 2))
+
+
+# ---------------------------------------------------------------------------
+# batched workload: many maps of uneven size, each with its own scene
+# ---------------------------------------------------------------------------
+
+
+def batch_grids(n_maps: int, seed: int, lo=(64, 64, 64), hi=(256, 256, 128),
+                voxel: float = 0.01) -> list:
+    """Grids with every axis uniform in [lo, hi] (ragged, not rounded)."""
+    g = rng(seed)
+    out = []
+    for _ in range(n_maps):
+        nx, ny, nz = (int(g.integers(lo[i], hi[i] + 1)) for i in range(3))
+        out.append(Grid(nx, ny, nz, (0.0, 0.0, 0.0), voxel))
+    return out
+
+
+@dataclasses.dataclass
+class BatchInputs:
+    grids: list
+    clouds: list              # float32 [n_m, 3] camera frame, one per map
+    T_map_cam: list           # float32 [12] per map
+    robots: list              # Robot per map (compact arm at the map centre)
+    lookahead: list           # float64 [S, 7] joint states per map
+    sphere_links: np.ndarray  # spheres on links 4..7 (shared layout)
+    sphere_local: list        # per map: centres in link frames
+    sphere_radii: list        # per map: float32 [m]
+    centres: list             # per map: float32 [S, m, 3] map-frame centres
+
+
+def batch_inputs(seed: int = 0, n_maps: int = 32, n_states: int = 16, min_points: int = 50_000,
+                 max_points: int = 300_000, n_spheres: int = 20, grids=None) -> BatchInputs:
+    """Batched cycle: per map its own depth frame subsampled to a point count
+    uniform in [min_points, max_points], an arm at the map centre, and
+    n_states look-ahead joint states q + U[-0.1, 0.1] rad per joint."""
+    g = rng(seed)
+    grids = grids if grids is not None else batch_grids(n_maps, seed)
+    clouds, Ts, robots, look, locs, rads, cents = [], [], [], [], [], [], []
+    li = None
+    for m, grid in enumerate(grids):
+        ext = np.array(grid.extent)
+        cam = Camera(position=(ext[0] / 2, -0.4, 0.78 * ext[2]))
+        scene = make_scene(grid, seed * 1000 + m)
+        pts = depth_frame(cam, scene, 0, seed * 1000 + m)
+        k = int(g.integers(min_points, max_points + 1))
+        sel = np.sort(g.choice(pts.shape[0], size=min(k, pts.shape[0]), replace=False))
+        clouds.append(np.ascontiguousarray(pts[sel]))
+        Ts.append(cam.T_map_cam())
+        robot = compact_robot(seed * 1000 + m, base=tuple(ext / 2))
+        robots.append(robot)
+        q0 = random_joint_states(1, seed * 1000 + m)[0]
+        qs = q0[None, :] + g.uniform(-0.1, 0.1, size=(n_states, 7))
+        look.append(qs)
+        li, cs, rs = sphere_set(robot, range(1, 8), n_spheres)
+        locs.append(cs)
+        rads.append(rs.astype(np.float32))
+        cents.append(np.stack([sphere_centres(robot, q, li, cs) for q in qs]))
+    return BatchInputs(grids, clouds, Ts, robots, look, li, locs, rads, cents)

@@ -1,0 +1,130 @@
+"""Batched EDT (many maps of uneven size in one persistent launch) against
+the CPU oracle map by map, every batch tiling, the batch autotuner, graph
+replays of a batch, and argument errors."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2407_02363_amd import edt, inputs
+from tests.gpu_util import dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def run_batch(occs, grids, tuning=None):
+    d = dev()
+    o = [torch.from_numpy(np.ascontiguousarray(x).ravel()).to(d) for x in occs]
+    d2 = [torch.full((x.size,), -7, dtype=torch.int32, device=d) for x in occs]
+    st = [torch.full((x.size,), -7, dtype=torch.int32, device=d) for x in occs]
+    maps = edt.batch_maps(grids, o, d2, st)
+    ws = edt.new_batch_workspace(len(grids), d)
+    edt.edt_compute_batched(maps, ws, tuning)
+    torch.cuda.synchronize()
+    assert not edt.edt_batch_status(ws)
+    return ([a.cpu().numpy().reshape(x.shape) for a, x in zip(d2, occs)],
+            [a.cpu().numpy().reshape(x.shape) for a, x in zip(st, occs)], (o, d2, st, maps, ws))
+
+
+def mixed_batch(seed):
+    r = inputs.rng(seed)
+    shapes = [(1, 1, 1), (3, 5, 7), (17, 64, 64), (40, 70, 130), (64, 128, 128), (128, 97, 65),
+              (9, 256, 31), (100, 100, 100), (33, 33, 33), (5, 200, 192)]
+    occs = []
+    for i, sh in enumerate(shapes):
+        dens = [0.0, 0.3, 0.01, 0.002, 0.05, 0.0005, 0.02, 0.001, 1.0, 0.01][i]
+        occs.append(inputs.random_grid(sh, dens, seed * 100 + i))
+    occs[7] = inputs.single_site_grid((100, 100, 100), (3, 97, 50))
+    grids = [inputs.Grid(sh[2], sh[1], sh[0]) for sh in shapes]
+    return occs, grids
+
+
+def check(occs, d2s, sites, oracle_lib, tag):
+    for i, occ in enumerate(occs):
+        rd2, rsite = oracle_lib.edt(occ)
+        assert np.array_equal(d2s[i], rd2), f"{tag}: map {i} {occ.shape} d2"
+        assert np.array_equal(sites[i], rsite), f"{tag}: map {i} {occ.shape} site"
+
+
+def test_mixed_batch_matches_oracle(oracle_lib):
+    occs, grids = mixed_batch(1)
+    say(f"[batch] mixed {len(occs)} maps")
+    d2s, sites, _ = run_batch(occs, grids)
+    check(occs, d2s, sites, oracle_lib, "mixed")
+
+
+@pytest.mark.parametrize("tiles", [(16, 16), (16, 32), (16, 64), (32, 16), (32, 32), (32, 64)])
+def test_every_batch_tiling(oracle_lib, tiles):
+    occs, grids = mixed_batch(2)
+    say(f"[batch] tiles {tiles}")
+    d2s, sites, _ = run_batch(occs, grids, tiles)
+    check(occs, d2s, sites, oracle_lib, f"tiles {tiles}")
+
+
+def test_batched_cycle_maps(oracle_lib):
+    """Uneven maps filled from their own depth frames (the batched workload)."""
+    bi = inputs.batch_inputs(seed=3, n_maps=6, n_states=2, min_points=20_000, max_points=60_000)
+    occs = []
+    for g, pts, T in zip(bi.grids, bi.clouds, bi.T_map_cam):
+        occ = np.zeros(g.shape, np.uint8)
+        oracle_lib.insert_points(g, occ, pts, T)
+        occs.append(occ)
+    say(f"[batch] cycle maps {[g.shape for g in bi.grids]}")
+    d2s, sites, _ = run_batch(occs, bi.grids)
+    check(occs, d2s, sites, oracle_lib, "cycle maps")
+
+
+def test_batch_autotune(oracle_lib):
+    occs, grids = mixed_batch(4)
+    d = dev()
+    o = [torch.from_numpy(x.ravel()).to(d) for x in occs]
+    d2 = [torch.empty(x.size, dtype=torch.int32, device=d) for x in occs]
+    st = [torch.empty(x.size, dtype=torch.int32, device=d) for x in occs]
+    maps = edt.batch_maps(grids, o, d2, st)
+    ws = edt.new_batch_workspace(len(grids), d)
+    tiles, us = edt.edt_autotune_batched(maps, ws, reps=2)
+    say(f"[batch] autotune -> {tiles} {us:.1f} us")
+    check(occs, [a.cpu().numpy().reshape(x.shape) for a, x in zip(d2, occs)],
+          [a.cpu().numpy().reshape(x.shape) for a, x in zip(st, occs)], oracle_lib, "autotuned")
+
+
+def test_batch_graph_replays(oracle_lib):
+    occs, grids = mixed_batch(5)
+    d2s, sites, (o, d2, st, maps, ws) = run_batch(occs, grids)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        edt.edt_compute_batched(maps, ws)
+    for rep in range(3):
+        for a in d2 + st:
+            a.fill_(-7)
+        torch.cuda.synchronize()
+        say(f"[batch] graph replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        got_d2 = [a.cpu().numpy().reshape(x.shape) for a, x in zip(d2, occs)]
+        got_st = [a.cpu().numpy().reshape(x.shape) for a, x in zip(st, occs)]
+        for i in range(len(occs)):
+            assert np.array_equal(got_d2[i], d2s[i]) and np.array_equal(got_st[i], sites[i])
+        # eager work between replays
+        edt.edt_compute(grids[4], o[4], d2[4], st[4])
+        torch.cuda.synchronize()
+
+
+def test_batch_errors():
+    d = dev()
+    ws = edt.new_batch_workspace(2, d)
+    o = torch.zeros(8, dtype=torch.uint8, device=d)
+    a = torch.zeros(8, dtype=torch.int32, device=d)
+    g = inputs.Grid(2, 2, 2)
+    maps = edt.batch_maps([g], [o], [a], [a.clone()])
+    with pytest.raises(edt.EdtError) as e:
+        edt.edt_compute_batched(maps, ws[:4])
+    assert e.value.status == -3
+    big = inputs.Grid(600, 1, 1)
+    o2 = torch.zeros(600, dtype=torch.uint8, device=d)
+    b = torch.zeros(600, dtype=torch.int32, device=d)
+    with pytest.raises(edt.EdtError) as e:
+        edt.edt_compute_batched(edt.batch_maps([big], [o2], [b], [b.clone()]), ws)
+    assert e.value.status == -5
+    with pytest.raises(edt.EdtError) as e:
+        edt.edt_compute_batched(maps, ws, (64, 64))
+    assert e.value.status == -5
