@@ -128,3 +128,42 @@ def test_batch_errors():
     with pytest.raises(edt.EdtError) as e:
         edt.edt_compute_batched(maps, ws, (64, 64))
     assert e.value.status == -5
+
+
+def test_batch_cycle_plain_batched_graph(oracle_lib):
+    """The batched cycle: per-map launches, one persistent launch, and the
+    graph-captured batched cycle give the same bytes as the oracle."""
+    from paper_2407_02363_amd.batch_cycle import BatchCycle
+    bi = inputs.batch_inputs(seed=6, n_maps=5, n_states=3, min_points=10_000, max_points=40_000)
+    bc = BatchCycle(bi)
+    refs = []
+    for i, g in enumerate(bi.grids):
+        occ = np.zeros(g.shape, np.uint8)
+        oracle_lib.insert_points(g, occ, bi.clouds[i], bi.T_map_cam[i])
+        d2, site = oracle_lib.edt(occ)
+        c = bi.centres[i].reshape(-1, 3)
+        r = np.tile(bi.sphere_radii[i], bi.centres[i].shape[0])
+        refs.append((d2, site, oracle_lib.query_spheres(g, d2, site, c, r)))
+
+    def verify(tag):
+        torch.cuda.synchronize()
+        for i, g in enumerate(bi.grids):
+            assert np.array_equal(bc.d2[i].cpu().numpy().reshape(g.shape), refs[i][0]), (tag, i)
+            assert np.array_equal(bc.site[i].cpu().numpy().reshape(g.shape), refs[i][1]), (tag, i)
+            assert np.array_equal(bc.out[i].cpu().numpy().view(np.uint32), refs[i][2]), (tag, i)
+
+    say("[batch cycle] plain")
+    bc.run_plain()
+    verify("plain")
+    say("[batch cycle] batched")
+    bc.run_batched()
+    verify("batched")
+    graph = bc.capture(bc.run_batched)
+    for rep in range(3):
+        for t in bc.d2 + bc.site:
+            t.fill_(-7)
+        say(f"[batch cycle] graph replay {rep}")
+        graph.replay()
+        verify(f"graph {rep}")
+        bc.run_plain()
+        torch.cuda.synchronize()
