@@ -1,0 +1,110 @@
+/*
+ * sdf_mlp.h -- C ABI of the learned self-distance surrogate in libedtmi.so.
+ *
+ * A small MLP maps a joint state q (7 joints) to the distance, in voxels,
+ * between each of 12 arm bounding spheres and the self-collision obstacle
+ * set -- the task variable x_s of Eq. selftaskvar (Sec. III-E) -- so that
+ * most look-ahead states skip the exact self-map EDT.  The paper has no
+ * such network: the exact self-map EDT (edt.h) produces its training labels,
+ * stays the fallback for every state whose prediction lies within the
+ * safety margin plus the network's measured maximum error, and is the judge
+ * of that error.
+ *
+ * Network: input [sin q1, cos q1, ..., sin q7, cos q7] -> 256 -> 256 -> 256
+ * -> 12, ReLU between layers.  BF16 inputs, weights and hidden activations
+ * (round to nearest even), FP32 accumulation on the matrix cores (MFMA),
+ * FP32 biases, FP32 master weights and Adam moments, mean squared error.
+ *
+ * Parameters live in ONE flat float32 block of SDF_MLP_PARAMS values at the
+ * fixed offsets below (weights W[out][in] row-major, the input dimension
+ * padded to 32 and the output dimension to 32 with zeros that stay zero),
+ * plus a bfloat16 copy of the same block (sdf_mlp_pack / sdf_mlp_adam keep
+ * it in step) that the matrix kernels read.  Gradients use the same layout.
+ *
+ * Conventions as in edt.h: device pointers, caller-owned buffers, stream as
+ * void*, nothing allocated, negative status on error.  Any batch >= 1 works:
+ * the workspace pads it to a multiple of 64 rows internally.
+ */
+#ifndef EDTMI_SDF_MLP_H
+#define EDTMI_SDF_MLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDF_MLP_JOINTS 7
+#define SDF_MLP_IN 14
+#define SDF_MLP_HIDDEN 256
+#define SDF_MLP_OUT 12
+#define SDF_MLP_IN_PAD 32
+#define SDF_MLP_OUT_PAD 32
+
+enum {
+    SDF_MLP_W1 = 0,        /* [256][32]  */
+    SDF_MLP_B1 = 8192,     /* [256]      */
+    SDF_MLP_W2 = 8448,     /* [256][256] */
+    SDF_MLP_B2 = 73984,    /* [256]      */
+    SDF_MLP_W3 = 74240,    /* [256][256] */
+    SDF_MLP_B3 = 139776,   /* [256]      */
+    SDF_MLP_W4 = 140032,   /* [32][256]  */
+    SDF_MLP_B4 = 148224,   /* [32]       */
+    SDF_MLP_PARAMS = 148256
+};
+
+/* Workspace bytes for a batch (encoded inputs, saved activations, outputs,
+ * gradients of the backward pass, loss partial sums). */
+size_t sdf_mlp_workspace_bytes(int32_t batch);
+
+/* w16 = bfloat16(master), element by element (round to nearest even). */
+int sdf_mlp_pack(const float* master, uint16_t* w16, void* stream);
+
+/*
+ * sdf_mlp_forward -- predicted distances for `batch` joint states.
+ *   w16     bfloat16 parameter block (weights read from it)
+ *   master  float32 parameter block (biases read from it)
+ *   q       float32 [batch][7] joint angles, radians
+ *   y       float32 [batch][12] out, voxels (NULL: keep only in ws)
+ * Saves the encoded inputs and hidden activations in ws for
+ * sdf_mlp_backward.
+ */
+int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, int32_t batch,
+                    float* y, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * sdf_mlp_backward -- gradients of the mean squared error of the last
+ * sdf_mlp_forward on ws against target (float32 [batch][12]).
+ *   grad  float32 parameter-block layout, fully overwritten.
+ *   loss  float32 device scalar out (nullable): the mean squared error.
+ * dY and every masked upstream gradient are rounded to bfloat16 before
+ * they enter a matrix product; weight gradients reduce over the batch in a
+ * fixed order (no atomics), so two runs give identical bits.
+ */
+int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t batch, float* grad,
+                     float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * sdf_mlp_adam -- one Adam step (bias-corrected; step counts from 1) on
+ * the float32 master block with moments m, v (same layout, start at zero),
+ * then refresh the bfloat16 copy w16.
+ */
+int sdf_mlp_adam(float* master, uint16_t* w16, float* m, float* v, const float* grad,
+                 int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/*
+ * sdf_mlp_fallback -- the exact-EDT fallback rule.  State b needs the exact
+ * self-map transform when some sphere i has predicted clearance
+ * y[b][i] * voxel - radii[i] below margin + eps_vox * voxel (metres), i.e.
+ * within the safety margin once the surrogate's worst error is allowed for.
+ *   need   int32 [batch] out: 1 = run the exact EDT for this state.
+ *   count  int32 device scalar out: number of such states.
+ */
+int sdf_mlp_fallback(const float* y, const float* radii, int32_t batch, float voxel, float margin,
+                     float eps_vox, int32_t* need, int32_t* count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDTMI_SDF_MLP_H */

@@ -122,6 +122,7 @@ def adam(master, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 def needs_exact(pred_vox, radii_m, voxel, margin_m, eps_vox):
     """Exact-EDT fallback rule: a state needs the exact self-map transform when
     any sphere's predicted clearance, pred * voxel - r, is below the safety
-    margin plus the surrogate's measured maximum error."""
+    margin plus the surrogate's measured maximum error (or is not a number)."""
     clearance = np.asarray(pred_vox, np.float64) * voxel - np.asarray(radii_m, np.float64)[None, :]
-    return (clearance < margin_m + eps_vox * voxel).any(axis=1)
+    # a NaN prediction is never trusted
+    return (~(clearance >= margin_m + eps_vox * voxel)).any(axis=1)

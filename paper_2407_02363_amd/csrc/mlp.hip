@@ -1,0 +1,493 @@
+// Learned self-distance surrogate: BF16 MFMA kernels for the forward pass,
+// the backward pass and Adam, plus the exact-EDT fallback rule.
+//
+// Every matrix product is one kernel, k_gemm: a 64 x 64 tile per 256-thread
+// work-group, 32 x 32 per wave as 2 x 2 blocks of v_mfma_f32_16x16x32_bf16,
+// fed straight from global memory (all operands are L2-resident: at most
+// 4096 x 256 bf16).  Lane l of an MFMA holds A[l % 16][8 (l / 16) + i],
+// B[8 (l / 16) + i][l % 16] and C[4 (l / 16) + i][l % 16].  The epilogue
+// decides what a product becomes:
+//   HID  hidden layer:  bf16(relu(acc + bias))
+//   OUT  output layer:  acc + bias (float32)
+//   DX   upstream gradient: bf16(acc masked where the layer input h > 0)
+//   DW   weight gradient:   acc (float32), the reduction over the batch is
+//        the product's own K loop, so the order is fixed.
+#include "common.h"
+#include "sdf_mlp.h"
+
+namespace edtmi {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int HID = SDF_MLP_HIDDEN;
+constexpr int INP = SDF_MLP_IN_PAD;
+constexpr int OUTP = SDF_MLP_OUT_PAD;
+constexpr int ROW_ALIGN = 64;
+
+__host__ __device__ inline int padded_rows(int b) { return (b + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
+
+// float -> bfloat16 bits, round to nearest even (NaN -> quiet NaN)
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0u;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Workspace layout (bytes) for padded batch P.
+struct WsLayout {
+    size_t x, h1, h2, h3, y, dy, dpa, dpb, part, total;
+};
+
+__host__ __device__ inline WsLayout ws_layout(int P)
+{
+    WsLayout w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    w.x = take((size_t)P * INP * 2);
+    w.h1 = take((size_t)P * HID * 2);
+    w.h2 = take((size_t)P * HID * 2);
+    w.h3 = take((size_t)P * HID * 2);
+    w.y = take((size_t)P * OUTP * 4);
+    w.dy = take((size_t)P * OUTP * 2);
+    w.dpa = take((size_t)P * HID * 2);
+    w.dpb = take((size_t)P * HID * 2);
+    w.part = take(1024 * 4);
+    w.total = o;
+    return w;
+}
+
+enum { EPI_HID = 0, EPI_OUT = 1, EPI_DX = 2, EPI_DW = 3 };
+
+struct GemmArgs {
+    const uint16_t* A;
+    int lda;
+    const uint16_t* B;
+    int ldb;
+    int M, N, K;           // K is a multiple of 32
+    const float* bias;     // HID / OUT
+    const uint16_t* mask;  // DX: layer input h, [M][ldm]
+    int ldm;
+    uint16_t* out16;       // HID / DX
+    float* out32;          // OUT / DW
+    int ldo;
+};
+
+// C[m][n] = sum_k A(m, k) B(k, n) with A(m, k) = TA ? A[k][m] : A[m][k] and
+// B(k, n) = TB ? B[n][k] : B[k][n].
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
+{
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int r = lane & 15;
+    const int kq = (lane >> 4) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
+        const int k = k0 + kq;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int m = m0 + 16 * i + r;
+            if (m < g.M) {
+                if constexpr (!TA) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(g.A + (size_t)m * g.lda + k);
+                    a[i] = __builtin_bit_cast(bf16x8, v);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        a[i][e] = __builtin_bit_cast(__bf16, g.A[(size_t)(k + e) * g.lda + m]);
+                }
+            } else {
+                a[i] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + 16 * j + r;
+            if (n < g.N) {
+                if constexpr (TB) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(g.B + (size_t)n * g.ldb + k);
+                    b[j] = __builtin_bit_cast(bf16x8, v);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        b[j][e] = __builtin_bit_cast(__bf16, g.B[(size_t)(k + e) * g.ldb + n]);
+                }
+            } else {
+                b[j] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + 16 * j + r;
+                if (m >= g.M || n >= g.N) continue;
+                const float v = acc[i][j][e];
+                if constexpr (EPI == EPI_HID) {
+                    const float z = v + g.bias[n];
+                    g.out16[(size_t)m * g.ldo + n] = f2bf(z > 0.0f ? z : 0.0f);
+                } else if constexpr (EPI == EPI_OUT) {
+                    g.out32[(size_t)m * g.ldo + n] = v + g.bias[n];
+                } else if constexpr (EPI == EPI_DX) {
+                    const bool on = bf2f(g.mask[(size_t)m * g.ldm + n]) > 0.0f;
+                    g.out16[(size_t)m * g.ldo + n] = f2bf(on ? v : 0.0f);
+                } else {
+                    g.out32[(size_t)m * g.ldo + n] = v;
+                }
+            }
+}
+
+// x = [sin q1, cos q1, ..., sin q7, cos q7, 0 ...] in bf16; padded rows 0
+__global__ void k_encode(const float* __restrict__ q, int batch, int P, uint16_t* __restrict__ x)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * INP) return;
+    const int b = i / INP, c = i % INP;
+    float v = 0.0f;
+    if (b < batch && c < 2 * SDF_MLP_JOINTS) {
+        const float a = q[b * SDF_MLP_JOINTS + (c >> 1)];
+        v = (c & 1) ? cosf(a) : sinf(a);
+    }
+    x[i] = f2bf(v);
+}
+
+// y32 [P][32] -> y [batch][12]
+__global__ void k_copy_out(const float* __restrict__ y32, int batch, float* __restrict__ y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= batch * SDF_MLP_OUT) return;
+    y[i] = y32[(i / SDF_MLP_OUT) * OUTP + i % SDF_MLP_OUT];
+}
+
+// dY = bf16(2 (y - t) / (batch * 12)) on valid entries, 0 elsewhere; block
+// partial sums of (y - t)^2 in a fixed order
+__global__ __launch_bounds__(256) void k_loss_dy(const float* __restrict__ y32,
+                                                 const float* __restrict__ t, int batch, int P,
+                                                 uint16_t* __restrict__ dy, float* __restrict__ part)
+{
+    __shared__ float red[256];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float scale = 2.0f / (float)(batch * SDF_MLP_OUT);
+    float sq = 0.0f;
+    if (i < P * OUTP) {
+        const int b = i / OUTP, c = i % OUTP;
+        float g = 0.0f;
+        if (b < batch && c < SDF_MLP_OUT) {
+            const float d = y32[i] - t[b * SDF_MLP_OUT + c];
+            sq = d * d;
+            g = d * scale;
+        }
+        dy[i] = f2bf(g);
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ part, int nparts,
+                                                    int batch, float* __restrict__ loss)
+{
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < nparts; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / (float)(batch * SDF_MLP_OUT);
+}
+
+// db[n] = sum over the P rows of dp[b][n] (bf16), one thread per column, in
+// row order
+__global__ void k_colsum(const uint16_t* __restrict__ dp, int P, int N, int ld, float* __restrict__ db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int b = 0; b < P; ++b) s += bf2f(dp[(size_t)b * ld + n]);
+    db[n] = s;
+}
+
+__global__ void k_pack(const float* __restrict__ master, uint16_t* __restrict__ w16, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w16[i] = f2bf(master[i]);
+}
+
+__global__ void k_adam(float* __restrict__ w, uint16_t* __restrict__ w16, float* __restrict__ m,
+                       float* __restrict__ v, const float* __restrict__ g, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    w16[i] = f2bf(wi);
+}
+
+__global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ y,
+                                                  const float* __restrict__ radii, int batch,
+                                                  float voxel, float thresh, int* __restrict__ need,
+                                                  int* __restrict__ count)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int flag = 0;
+    if (b < batch) {
+        for (int i = 0; i < SDF_MLP_OUT; ++i) {
+            const float c = y[b * SDF_MLP_OUT + i] * voxel - radii[i];
+            if (!(c >= thresh)) flag = 1;   // NaN predictions also fall back
+        }
+        need[b] = flag;
+    }
+    const unsigned long long bal = __ballot(flag);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(count, (int)__popcll(bal));
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+template <bool TA, bool TB, int EPI>
+int gemm(const GemmArgs& a, hipStream_t st)
+{
+    if (a.K % 32) {
+        set_error("k_gemm: K=%d is not a multiple of 32", a.K);
+        return EDT_ERR_ARG;
+    }
+    const dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, st, a);
+    return check_launch("k_gemm");
+}
+
+GemmArgs args0()
+{
+    GemmArgs a{};
+    return a;
+}
+
+}  // namespace
+
+}  // namespace edtmi
+
+using namespace edtmi;
+
+extern "C" {
+
+size_t sdf_mlp_workspace_bytes(int32_t batch)
+{
+    if (batch < 1) return 0;
+    return ws_layout(padded_rows(batch)).total;
+}
+
+int sdf_mlp_pack(const float* master, uint16_t* w16, void* stream)
+{
+    if (!master || !w16) {
+        set_error("sdf_mlp_pack: NULL pointer");
+        return EDT_ERR_ARG;
+    }
+    hipLaunchKernelGGL(k_pack, dim3((SDF_MLP_PARAMS + 255) / 256), dim3(256), 0, as_stream(stream),
+                       master, w16, (int)SDF_MLP_PARAMS);
+    return check_launch("k_pack");
+}
+
+int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, int32_t batch,
+                    float* y, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!w16 || !master || !q || !ws || batch < 1) {
+        set_error("sdf_mlp_forward: NULL pointer or batch < 1");
+        return EDT_ERR_ARG;
+    }
+    const int P = padded_rows(batch);
+    const WsLayout L = ws_layout(P);
+    if (ws_bytes < L.total) {
+        set_error("sdf_mlp_forward: workspace %zu < %zu bytes", ws_bytes, L.total);
+        return EDT_ERR_WORKSPACE;
+    }
+    char* w = static_cast<char*>(ws);
+    uint16_t* x = reinterpret_cast<uint16_t*>(w + L.x);
+    uint16_t* h[3] = {reinterpret_cast<uint16_t*>(w + L.h1), reinterpret_cast<uint16_t*>(w + L.h2),
+                      reinterpret_cast<uint16_t*>(w + L.h3)};
+    float* y32 = reinterpret_cast<float*>(w + L.y);
+    const hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_encode, dim3((P * INP + 255) / 256), dim3(256), 0, st, q, (int)batch, P, x);
+    int rc = check_launch("k_encode");
+    if (rc) return rc;
+    const int woff[4] = {SDF_MLP_W1, SDF_MLP_W2, SDF_MLP_W3, SDF_MLP_W4};
+    const int boff[4] = {SDF_MLP_B1, SDF_MLP_B2, SDF_MLP_B3, SDF_MLP_B4};
+    const uint16_t* in = x;
+    int kin = INP;
+    for (int l = 0; l < 4; ++l) {
+        GemmArgs a = args0();
+        a.A = in;
+        a.lda = kin;
+        a.B = w16 + woff[l];
+        a.ldb = kin;
+        a.M = P;
+        a.K = kin;
+        a.bias = master + boff[l];
+        if (l < 3) {
+            a.N = HID;
+            a.out16 = h[l];
+            a.ldo = HID;
+            rc = gemm<false, true, EPI_HID>(a, st);
+            in = h[l];
+            kin = HID;
+        } else {
+            a.N = OUTP;
+            a.out32 = y32;
+            a.ldo = OUTP;
+            rc = gemm<false, true, EPI_OUT>(a, st);
+        }
+        if (rc) return rc;
+    }
+    if (y) {
+        hipLaunchKernelGGL(k_copy_out, dim3((batch * SDF_MLP_OUT + 255) / 256), dim3(256), 0, st, y32,
+                           (int)batch, y);
+        rc = check_launch("k_copy_out");
+    }
+    return rc;
+}
+
+int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t batch, float* grad,
+                     float* loss, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!w16 || !target || !grad || !ws || batch < 1) {
+        set_error("sdf_mlp_backward: NULL pointer or batch < 1");
+        return EDT_ERR_ARG;
+    }
+    const int P = padded_rows(batch);
+    const WsLayout L = ws_layout(P);
+    if (ws_bytes < L.total) {
+        set_error("sdf_mlp_backward: workspace %zu < %zu bytes", ws_bytes, L.total);
+        return EDT_ERR_WORKSPACE;
+    }
+    char* w = static_cast<char*>(ws);
+    const uint16_t* act[4] = {reinterpret_cast<uint16_t*>(w + L.x), reinterpret_cast<uint16_t*>(w + L.h1),
+                              reinterpret_cast<uint16_t*>(w + L.h2), reinterpret_cast<uint16_t*>(w + L.h3)};
+    const float* y32 = reinterpret_cast<float*>(w + L.y);
+    uint16_t* dy = reinterpret_cast<uint16_t*>(w + L.dy);
+    uint16_t* dp[2] = {reinterpret_cast<uint16_t*>(w + L.dpa), reinterpret_cast<uint16_t*>(w + L.dpb)};
+    float* part = reinterpret_cast<float*>(w + L.part);
+    const hipStream_t st = as_stream(stream);
+    const int nblk = (P * OUTP + 255) / 256;
+    if (nblk > 1024) {
+        set_error("sdf_mlp_backward: batch too large for the loss reduction");
+        return EDT_ERR_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(k_loss_dy, dim3(nblk), dim3(256), 0, st, y32, target, (int)batch, P, dy, part);
+    int rc = check_launch("k_loss_dy");
+    if (rc) return rc;
+    if (loss) {
+        hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nblk, (int)batch, loss);
+        if ((rc = check_launch("k_loss_final"))) return rc;
+    }
+    const int woff[4] = {SDF_MLP_W1, SDF_MLP_W2, SDF_MLP_W3, SDF_MLP_W4};
+    const int boff[4] = {SDF_MLP_B1, SDF_MLP_B2, SDF_MLP_B3, SDF_MLP_B4};
+    const int nout[4] = {HID, HID, HID, OUTP};
+    const int nin[4] = {INP, HID, HID, HID};
+    const uint16_t* up = dy;   // upstream gradient of layer l's output, [P][nout]
+    for (int l = 3; l >= 0; --l) {
+        // dW_l = up^T act_l : M = nout, N = nin, K = P (rows of the batch)
+        GemmArgs a = args0();
+        a.A = up;
+        a.lda = nout[l];
+        a.B = act[l];
+        a.ldb = nin[l];
+        a.M = nout[l];
+        a.N = nin[l];
+        a.K = P;
+        a.out32 = grad + woff[l];
+        a.ldo = nin[l];
+        if ((rc = gemm<true, false, EPI_DW>(a, st))) return rc;
+        hipLaunchKernelGGL(k_colsum, dim3((nout[l] + 255) / 256), dim3(256), 0, st, up, P, nout[l],
+                           nout[l], grad + boff[l]);
+        if ((rc = check_launch("k_colsum"))) return rc;
+        if (l == 0) break;
+        // upstream of layer l-1: (up W_l) masked where act_l > 0
+        GemmArgs d = args0();
+        d.A = up;
+        d.lda = nout[l];
+        d.B = w16 + woff[l];
+        d.ldb = nin[l];
+        d.M = P;
+        d.N = nin[l];
+        d.K = nout[l];
+        d.mask = act[l];
+        d.ldm = nin[l];
+        d.out16 = dp[l & 1];
+        d.ldo = nin[l];
+        if ((rc = gemm<false, false, EPI_DX>(d, st))) return rc;
+        up = dp[l & 1];
+    }
+    return EDT_OK;
+}
+
+int sdf_mlp_adam(float* master, uint16_t* w16, float* m, float* v, const float* grad, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void* stream)
+{
+    if (!master || !w16 || !m || !v || !grad || step < 1) {
+        set_error("sdf_mlp_adam: NULL pointer or step < 1");
+        return EDT_ERR_ARG;
+    }
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    hipLaunchKernelGGL(k_adam, dim3((SDF_MLP_PARAMS + 255) / 256), dim3(256), 0, as_stream(stream),
+                       master, w16, m, v, grad, (int)SDF_MLP_PARAMS, lr, beta1, beta2, eps, c1, c2);
+    return check_launch("k_adam");
+}
+
+int sdf_mlp_fallback(const float* y, const float* radii, int32_t batch, float voxel, float margin,
+                     float eps_vox, int32_t* need, int32_t* count, void* stream)
+{
+    if (!y || !radii || !need || !count || batch < 1 || !(voxel > 0.0f)) {
+        set_error("sdf_mlp_fallback: bad argument");
+        return EDT_ERR_ARG;
+    }
+    const hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, count);
+    int rc = check_launch("k_zero_int");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_fallback, dim3((batch + 255) / 256), dim3(256), 0, st, y, radii, (int)batch,
+                       voxel, margin + eps_vox * voxel, need, count);
+    return check_launch("k_fallback");
+}
+
+}  // extern "C"

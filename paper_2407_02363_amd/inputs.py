@@ -326,6 +326,29 @@ class Robot:
             out[i, :, 3] = t
         return out
 
+    def fk_batch(self, qs) -> np.ndarray:
+        """Link frames for many joint states: float64 [N, 8, 3, 4]."""
+        qs = np.asarray(qs, dtype=np.float64)
+        n = qs.shape[0]
+        R = np.broadcast_to(rot_x(math.pi) if self.torso_down else np.eye(3), (n, 3, 3)).copy()
+        t = np.broadcast_to(np.asarray(self.base, np.float64), (n, 3)).copy()
+        out = np.zeros((n, self.n_links, 3, 4))
+        out[:, 0, :, :3] = R
+        out[:, 0, :, 3] = t
+        for i in range(1, self.n_links):
+            t = t + R[:, :, 2] * self.lengths[i - 1]
+            a = qs[:, i - 1]
+            c, s_ = np.cos(a), np.sin(a)
+            J = np.zeros((n, 3, 3))
+            if JOINT_AXES[i - 1] == "z":
+                J[:, 0, 0], J[:, 0, 1], J[:, 1, 0], J[:, 1, 1], J[:, 2, 2] = c, -s_, s_, c, 1.0
+            else:
+                J[:, 0, 0], J[:, 0, 2], J[:, 2, 0], J[:, 2, 2], J[:, 1, 1] = c, s_, -s_, c, 1.0
+            R = R @ J
+            out[:, i, :, :3] = R
+            out[:, i, :, 3] = t
+        return out
+
     def poses12(self, q) -> np.ndarray:
         f = self.fk(q)
         return f.reshape(self.n_links, 12).astype(np.float32)
@@ -341,9 +364,10 @@ def make_robot(seed: int, base=(1.28, 1.28, 0.3), r_lo=0.04, r_hi=0.08,
 
 
 def compact_robot(seed: int, base=(0.64, 0.64, 0.64)) -> Robot:
-    """Arm whose full reach fits a 128^3 map at 1 cm centred on its base."""
-    return make_robot(seed, base=base, r_lo=0.025, r_hi=0.04, l_lo=0.06,
-                      l_hi=0.085, torso_down=True)
+    """Arm whose full reach fits a 128^3 map at 1 cm centred on its base:
+    8 links of at most 7.5 cm plus a sphere overhang stay within 0.64 m."""
+    return make_robot(seed, base=base, r_lo=0.02, r_hi=0.035, l_lo=0.05,
+                      l_hi=0.075, torso_down=True)
 
 
 def random_joint_states(n: int, seed: int, limit_deg: float = 170.0) -> np.ndarray:
@@ -512,3 +536,56 @@ def batch_inputs(seed: int = 0, n_maps: int = 32, n_states: int = 16, min_points
         rads.append(rs.astype(np.float32))
         cents.append(np.stack([sphere_centres(robot, q, li, cs) for q in qs]))
     return BatchInputs(grids, clouds, Ts, robots, look, li, locs, rads, cents)
+
+
+# ---------------------------------------------------------------------------
+# learned self-distance surrogate: self-map workload
+# ---------------------------------------------------------------------------
+
+SELF_GRID = Grid(128, 128, 128, (0.0, 0.0, 0.0), 0.01)
+SELF_OBSTACLE_MASK = 0b0000_0011     # torso (link 0) and shoulder (link 1)
+SELF_SPHERE_LINKS = (4, 5, 6, 7)
+SELF_N_SPHERES = 12
+
+
+@dataclasses.dataclass
+class SelfMapSetup:
+    grid: Grid
+    robot: Robot
+    link_pts: np.ndarray
+    link_off: np.ndarray
+    mask: int
+    sphere_links: np.ndarray
+    sphere_local: np.ndarray
+    sphere_radii: np.ndarray
+
+
+def self_map_robot() -> Robot:
+    """The arm of the self-collision workload: a thick torso (link 0, 25 cm
+    long, 10 cm radius) rising from (0.64, 0.64, 0.35) m, a short shoulder
+    and six arm links.  From the shoulder at z = 0.60 m its whole reach,
+    sphere overhang included (0.595 m), stays inside the 1.28 m map."""
+    return Robot(base=np.array([0.64, 0.64, 0.35]),
+                 radii=np.array([0.10, 0.05, 0.04, 0.035, 0.03, 0.03, 0.025, 0.025]),
+                 lengths=np.array([0.25, 0.06, 0.12, 0.10, 0.10, 0.08, 0.06, 0.05]))
+
+
+def self_map_setup() -> SelfMapSetup:
+    """128^3 map at 1 cm around the arm, obstacle links 0-1 (the links not
+    in the allowed-collision set of the distal arm, Eq. selfclink) and 12
+    bounding spheres on links 4-7 (Sec. III-B rule, 3 per link)."""
+    g = SELF_GRID
+    robot = self_map_robot()
+    lp, lo = link_models(robot, g.voxel)
+    li, cs, rs = sphere_set(robot, SELF_SPHERE_LINKS, SELF_N_SPHERES)
+    assert len(rs) == SELF_N_SPHERES
+    return SelfMapSetup(g, robot, lp, lo, SELF_OBSTACLE_MASK, li, cs, rs.astype(np.float32))
+
+
+def sphere_centres_batch(robot: Robot, qs, links_idx, centres_link) -> np.ndarray:
+    """float32 [N, m, 3] map-frame sphere centres for many joint states."""
+    f = robot.fk_batch(qs)
+    fl = f[:, links_idx]          # [N, m, 3, 4]
+    R = fl[..., :3]
+    t = fl[..., 3]
+    return (np.einsum("nkij,kj->nki", R, centres_link) + t).astype(np.float32)

@@ -1,0 +1,92 @@
+"""Exact self-map distances at the arm's sphere centres for many joint states.
+
+For each state (Alg. 2 lines for the self map): ClearMap, insert the voxel
+models of the obstacle links O_L placed by the state's forward kinematics,
+compute the exact EDT, and read sqrt(d2) at every sphere centre
+(ExtractClosestObstaclePose).  States go in chunks of up to EDT_BATCH_MAX
+maps: one persistent batched EDT launch per chunk, and the whole chunk is
+replayed from a HIP graph whose pose and centre buffers are refilled before
+every replay.  These distances are the surrogate's labels and the judge of
+its error; the same path is the fallback when the surrogate is not trusted.
+Only orchestration lives here.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import edt, inputs
+
+
+class SelfMapLabeler:
+    def __init__(self, setup: "inputs.SelfMapSetup", chunk: int = 48, device="cuda:0",
+                 use_graph: bool = True):
+        self.s = setup
+        self.chunk = int(chunk)
+        self.dev = torch.device(device)
+        d = self.dev
+        g = setup.grid
+        n = g.n
+        c = self.chunk
+        self.occ = [torch.zeros(n, dtype=torch.uint8, device=d) for _ in range(c)]
+        self.d2 = [torch.empty(n, dtype=torch.int32, device=d) for _ in range(c)]
+        self.site = [torch.empty(n, dtype=torch.int32, device=d) for _ in range(c)]
+        self.poses = torch.zeros((c, setup.robot.n_links, 12), dtype=torch.float32, device=d)
+        self.centres = torch.zeros((c, len(setup.sphere_radii), 3), dtype=torch.float32, device=d)
+        self.radii = torch.from_numpy(setup.sphere_radii).to(d)
+        self.out = torch.empty((c, len(setup.sphere_radii), edt.SPHERE_RESULT_WORDS),
+                               dtype=torch.int32, device=d)
+        self.link_pts = torch.from_numpy(setup.link_pts).to(d)
+        self.maps = edt.batch_maps([g] * c, self.occ, self.d2, self.site)
+        self.ws = edt.new_batch_workspace(c, d)
+        self.graph = None
+        if use_graph:
+            self.run_chunk()
+            torch.cuda.synchronize(d)
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph, capture_error_mode="thread_local"):
+                self.run_chunk()
+            torch.cuda.synchronize(d)
+
+    def run_chunk(self, stream=None):
+        g = self.s.grid
+        for i in range(self.chunk):
+            edt.edt_clear(g, self.occ[i], stream)
+            edt.edt_insert_links(g, self.occ[i], self.link_pts, self.s.link_off, self.poses[i],
+                                 self.s.mask, stream)
+        edt.edt_compute_batched(self.maps, self.ws, stream=stream)
+        for i in range(self.chunk):
+            edt.edt_query_spheres(g, self.d2[i], self.site[i], self.centres[i], self.radii,
+                                  self.out[i], stream)
+
+    def stage(self, qs: np.ndarray):
+        """Host forward kinematics of many states -> device (poses, centres)."""
+        f = self.s.robot.fk_batch(qs)
+        poses = torch.from_numpy(f.reshape(len(qs), self.s.robot.n_links, 12).astype(np.float32))
+        cen = inputs.sphere_centres_batch(self.s.robot, qs, self.s.sphere_links, self.s.sphere_local)
+        return poses.to(self.dev), torch.from_numpy(cen).to(self.dev)
+
+    def distances(self, poses_dev, centres_dev, out_dev=None):
+        """sqrt(d2) (voxels) at every sphere centre for staged states:
+        float32 [N, m] on the device."""
+        n = poses_dev.shape[0]
+        m = centres_dev.shape[1]
+        res = out_dev if out_dev is not None else torch.empty((n, m), dtype=torch.float32,
+                                                              device=self.dev)
+        for s0 in range(0, n, self.chunk):
+            k = min(self.chunk, n - s0)
+            self.poses[:k].copy_(poses_dev[s0:s0 + k])
+            self.centres[:k].copy_(centres_dev[s0:s0 + k])
+            if k < self.chunk:   # the unused slots repeat the last state
+                self.poses[k:].copy_(poses_dev[s0 + k - 1].expand(self.chunk - k, -1, -1))
+                self.centres[k:].copy_(centres_dev[s0 + k - 1].expand(self.chunk - k, -1, -1))
+            if self.graph is not None:
+                self.graph.replay()
+            else:
+                self.run_chunk()
+            res[s0:s0 + k].copy_(self.out[:k, :, 6].view(torch.float32))
+        return res
+
+    def labels(self, qs: np.ndarray) -> torch.Tensor:
+        poses, cen = self.stage(qs)
+        return self.distances(poses, cen)

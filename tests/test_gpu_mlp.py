@@ -1,0 +1,247 @@
+"""The learned self-distance surrogate on the GPU against the CPU oracle.
+
+Forward, backward and Adam are compared with oracle/mlp_ref.py under the
+same bf16 precision plan; the device accumulates in float32 (the oracle in
+float64), so a bf16 result may differ by one unit in the last place where
+the float32 sum lands near a rounding boundary, and float32 results by
+float32 rounding.  Tolerances below follow from that.  The labels come from
+the exact self-map EDT and must match the oracle's transform bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_ref as M
+from paper_2407_02363_amd import inputs, mlp
+from paper_2407_02363_amd.surrogate import Surrogate
+from tests.gpu_util import dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def ws_views(ws, batch):
+    """Activations saved by sdf_mlp_forward, at the library's workspace
+    offsets (256-byte aligned regions in the documented order)."""
+    P = (batch + 63) // 64 * 64
+    sizes = [("x", P * 32 * 2), ("h1", P * 256 * 2), ("h2", P * 256 * 2), ("h3", P * 256 * 2),
+             ("y", P * 32 * 4)]
+    out, off = {}, 0
+    raw = ws.cpu().numpy()
+    for name, nbytes in sizes:
+        buf = raw[off:off + nbytes]
+        if name == "y":
+            out[name] = buf.view(np.float32).reshape(P, 32).astype(np.float64)
+        else:
+            cols = 32 if name == "x" else 256
+            out[name] = (buf.view(np.uint16).astype(np.uint32) << 16).view(np.float32).reshape(P, cols).astype(np.float64)
+        off += (nbytes + 255) // 256 * 256
+    return out
+
+
+def device_params(s: Surrogate):
+    """The parameters as the kernels see them: bf16 weights, f32 biases."""
+    w16 = s.w16.float().cpu().numpy().astype(np.float64)
+    master = s.master.cpu().numpy()
+    out = []
+    for (wo, bo, rows, cols), (ro, ci) in zip(mlp.LAYOUT, mlp.REAL):
+        W = w16[wo:wo + rows * cols].reshape(rows, cols)[:ro, :ci]
+        out.append((W, master[bo:bo + ro].astype(np.float64)))
+    return out
+
+
+def perturbed_surrogate(seed):
+    s = Surrogate(dev(), seed=seed, batch=512)
+    g = inputs.rng(seed + 100)
+    p = s.master.cpu().numpy()
+    for _, bo, rows, _ in mlp.LAYOUT:
+        p[bo:bo + rows] = g.normal(0, 0.1, rows)
+    # keep the padded output rows at zero
+    p[mlp.B4 + 12:mlp.B4 + 32] = 0
+    s.master.copy_(torch.from_numpy(p))
+    mlp.sdf_mlp_pack(s.master, s.w16)
+    return s
+
+
+def test_pack_is_round_to_nearest_even():
+    s = Surrogate(dev(), seed=1, batch=64)
+    torch.cuda.synchronize()
+    ref = M.bf16(s.master.cpu().numpy().astype(np.float64))
+    assert np.array_equal(s.w16.float().cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("batch", [1, 300, 512])
+def test_forward_matches_oracle(batch):
+    s = perturbed_surrogate(2)
+    q_np = inputs.random_joint_states(batch, 3).astype(np.float32)
+    q = torch.from_numpy(q_np).to(dev())
+    y = torch.empty((batch, 12), dtype=torch.float32, device=dev())
+    say(f"[mlp] forward batch={batch}")
+    mlp.sdf_mlp_forward(s.w16, s.master, q, y, s.ws)
+    torch.cuda.synchronize()
+    params = device_params(s)
+    acts = ws_views(s.ws, batch)
+    # inputs: bf16(sin / cos); the device's sinf may sit one bf16 step away
+    # from the float64 value only at rounding boundaries
+    x_ref = M.encode(q_np.astype(np.float64))
+    assert np.mean(acts["x"][:batch, :14] == x_ref) > 0.999
+    assert np.abs(acts["x"][:batch, :14] - x_ref).max() <= 2 ** -8
+    assert (acts["x"][:batch, 14:] == 0).all()
+    # every layer from the device's own inputs: bf16 outputs equal the
+    # oracle's or are one bf16 step away
+    ins = [acts["x"][:batch, :14], acts["h1"][:batch], acts["h2"][:batch], acts["h3"][:batch]]
+    outs = [acts["h1"][:batch], acts["h2"][:batch], acts["h3"][:batch], acts["y"][:batch, :12]]
+    for li, (W, b) in enumerate(params):
+        z = M.f32(ins[li] @ W.T + b)
+        if li < 3:
+            ref = M.bf16(np.maximum(z, 0))
+            got = outs[li]
+            step = np.maximum(np.abs(ref), 1e-30) * 2 ** -7
+            assert (np.abs(got - ref) <= step).all(), li
+            assert np.mean(got == ref) > 0.995, li
+        else:
+            got = outs[li]
+            assert np.allclose(got, z, rtol=1e-5, atol=1e-5 * np.abs(z).max())
+    assert np.array_equal(y.cpu().numpy(), acts["y"][:batch, :12].astype(np.float32))
+    # end to end from q: small relative to the output scale
+    y_ref, _ = M.forward(params, q_np.astype(np.float64))
+    scale = np.abs(y_ref).max() + 1e-6
+    assert np.abs(y.cpu().numpy() - y_ref).max() < 0.02 * scale
+
+
+def test_backward_matches_oracle():
+    batch = 320
+    s = perturbed_surrogate(4)
+    q_np = inputs.random_joint_states(batch, 5).astype(np.float32)
+    t_np = inputs.rng(6).uniform(0, 20, (batch, 12)).astype(np.float32)
+    q = torch.from_numpy(q_np).to(dev())
+    t = torch.from_numpy(t_np).to(dev())
+    y = torch.empty((batch, 12), dtype=torch.float32, device=dev())
+    mlp.sdf_mlp_forward(s.w16, s.master, q, y, s.ws)
+    mlp.sdf_mlp_backward(s.w16, t, s.grad, s.loss, s.ws)
+    torch.cuda.synchronize()
+    say("[mlp] backward")
+    params = device_params(s)
+    acts = ws_views(s.ws, batch)
+    a = [acts["x"][:batch, :14], acts["h1"][:batch], acts["h2"][:batch], acts["h3"][:batch]]
+    yd = y.cpu().numpy().astype(np.float64)
+    loss, dy = M.loss_and_dy(yd, t_np.astype(np.float64))
+    assert abs(float(s.loss.item()) - loss) <= 1e-5 * loss
+    grads = M.backward(params, a, dy)
+    g = s.grad.cpu().numpy()
+    for li, ((wo, bo, rows, cols), (ro, ci)) in enumerate(zip(mlp.LAYOUT, mlp.REAL)):
+        dW = g[wo:wo + rows * cols].reshape(rows, cols)
+        db = g[bo:bo + rows]
+        rdW, rdb = grads[li]
+        # padding gradients are exactly zero
+        assert (dW[ro:, :] == 0).all() and (dW[:, ci:] == 0).all() and (db[ro:] == 0).all()
+        err = np.abs(dW[:ro, :ci] - rdW).max()
+        assert err <= 2e-3 * np.abs(rdW).max() + 1e-7, (li, err, np.abs(rdW).max())
+        assert np.abs(db[:ro] - rdb).max() <= 2e-3 * np.abs(rdb).max() + 1e-7, li
+    # same inputs, same bits: the reductions have a fixed order
+    g1 = s.grad.clone()
+    mlp.sdf_mlp_forward(s.w16, s.master, q, y, s.ws)
+    mlp.sdf_mlp_backward(s.w16, t, s.grad, s.loss, s.ws)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, s.grad)
+
+
+def test_adam_matches_oracle():
+    s = Surrogate(dev(), seed=7, batch=64)
+    g = inputs.rng(8)
+    w = s.master.cpu().numpy().astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for step in range(1, 4):
+        gr = g.normal(0, 1, w.shape).astype(np.float32)
+        s.grad.copy_(torch.from_numpy(gr))
+        mlp.sdf_mlp_adam(s.master, s.w16, s.m, s.v, s.grad, step, 1e-3)
+        (w,), (m,), (v,) = M.adam([w], [gr.astype(np.float64)], [m], [v], step)
+    torch.cuda.synchronize()
+    got = s.master.cpu().numpy().astype(np.float64)
+    assert np.abs(got - w).max() < 1e-6
+    assert np.array_equal(s.w16.float().cpu().numpy().astype(np.float64), M.bf16(got))
+
+
+def test_fallback_kernel_matches_rule():
+    g = inputs.rng(9)
+    n = 5000
+    y_np = g.uniform(0, 25, (n, 12)).astype(np.float32)
+    y_np[17, 3] = np.nan
+    radii = g.uniform(0.02, 0.05, 12).astype(np.float32)
+    voxel, margin, eps = 0.01, 0.05, 1.7
+    s = Surrogate(dev(), seed=0, batch=64)
+    need, count = s.fallback(torch.from_numpy(y_np).to(dev()), torch.from_numpy(radii).to(dev()),
+                             voxel, margin, eps)
+    torch.cuda.synchronize()
+    ref = M.needs_exact(y_np, radii, voxel, margin, eps)
+    clear = y_np.astype(np.float64) * voxel - radii[None, :]
+    near = (np.abs(clear - (margin + eps * voxel)) < 1e-6).any(1)   # float32 ties
+    got = need.cpu().numpy().astype(bool)
+    assert np.array_equal(got[~near], ref[~near]) and got[17]
+    assert int(count.item()) == int(got.sum())
+
+
+def test_labeler_matches_oracle(oracle_lib):
+    from paper_2407_02363_amd.selfmap import SelfMapLabeler
+    st = inputs.self_map_setup()
+    lab = SelfMapLabeler(st, chunk=8, device=dev())
+    qs = inputs.random_joint_states(13, 11)   # one full chunk and a partial one
+    say("[mlp] labels")
+    got = lab.labels(qs).cpu().numpy()
+    g = st.grid
+    for k, q in enumerate(qs):
+        occ = np.zeros(g.shape, np.uint8)
+        oracle_lib.insert_links(g, occ, st.link_pts, st.link_off, st.robot.poses12(q), st.mask)
+        d2, site = oracle_lib.edt(occ)
+        c = inputs.sphere_centres(st.robot, q, st.sphere_links, st.sphere_local)
+        ref = oracle_lib.query_spheres(g, d2, site, c, st.sphere_radii).view(np.float32)[:, 6]
+        assert np.array_equal(got[k], ref), k
+
+
+def test_training_is_deterministic_and_learns():
+    from paper_2407_02363_amd.selfmap import SelfMapLabeler
+    st = inputs.self_map_setup()
+    lab = SelfMapLabeler(st, chunk=48, device=dev())
+    qs = inputs.random_joint_states(4096 * 2, 12)
+    y = lab.labels(qs)
+    q = torch.from_numpy(qs.astype(np.float32)).to(dev())
+    runs = []
+    for rep in range(2):
+        s = Surrogate(dev(), seed=13, batch=4096)
+        hist = s.train(q, y, epochs=12, lr=2e-3, seed=1)
+        say(f"[mlp] run {rep} loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+        runs.append((hist, s.master.clone()))
+    assert runs[0][0] == runs[1][0] and torch.equal(runs[0][1], runs[1][1])
+    assert runs[0][0][-1] < 0.2 * runs[0][0][0]
+
+
+def test_surrogate_gain_with_zero_misses():
+    """Trained on exact-EDT labels, the surrogate plus fallback rule never
+    calls a state safe that the exact transform puts inside the margin, and
+    skips the exact transform for a real share of the look-ahead states."""
+    from paper_2407_02363_amd.selfmap import SelfMapLabeler
+    st = inputs.self_map_setup()
+    lab = SelfMapLabeler(st, chunk=48, device=dev())
+    q_tr = inputs.random_joint_states(40960, 21)
+    q_va = inputs.random_joint_states(8192, 22)
+    q_te = inputs.random_joint_states(8192, 23)
+    say("[mlp] labelling 57k states")
+    y_tr, y_va, y_te = lab.labels(q_tr), lab.labels(q_va), lab.labels(q_te)
+    s = Surrogate(dev(), seed=3, batch=4096)
+    t = lambda a: torch.from_numpy(a.astype(np.float32)).to(dev())
+    hist = s.train(t(q_tr), y_tr, epochs=40, lr=2e-3, seed=2)
+    p_va = s.predict(t(q_va))
+    eps = float((p_va - y_va).abs().max().item())
+    p_te = s.predict(t(q_te))
+    radii = torch.from_numpy(st.sphere_radii).to(dev())
+    need, count = s.fallback(p_te, radii, st.grid.voxel, 0.05, eps)
+    torch.cuda.synchronize()
+    need = need.cpu().numpy().astype(bool)
+    exact_clear = y_te.cpu().numpy().astype(np.float64) * st.grid.voxel - st.sphere_radii[None, :]
+    truly_near = (exact_clear < 0.05).any(1)
+    misses = int((truly_near & ~need).sum())
+    skipped = 1.0 - need.mean()
+    say(f"[mlp] loss {hist[0]:.2f}->{hist[-1]:.3f}, eps_max {eps:.2f} vox, "
+        f"fallback {need.mean():.3f}, truly near {truly_near.mean():.3f}, misses {misses}")
+    assert misses == 0
+    assert skipped > 0.15
