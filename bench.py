@@ -162,6 +162,124 @@ def batched_workload(args, torch, edt, inputs, host_latency=True):
     return res
 
 
+def surrogate_workload(args, torch, inputs):
+    """Learned self-distance surrogate on the 128^3 self-map: exact-EDT
+    labels, GPU training, worst held-out error, and look-ahead evaluation
+    with the exact EDT alone vs surrogate plus exact fallback."""
+    import numpy as np
+    from paper_2407_02363_amd.selfmap import SelfMapLabeler
+    from paper_2407_02363_amd.surrogate import Surrogate
+
+    margin = 0.05
+    st = inputs.self_map_setup()
+    vox = st.grid.voxel
+    lab = SelfMapLabeler(st, chunk=48)
+    n_tr = args.surrogate_train
+    n_va = n_te = max(4096, n_tr // 8)
+    log(f"[bench] surrogate: labelling {n_tr + n_va + n_te} states with the exact self-map EDT")
+    q_tr, q_va, q_te = (inputs.random_joint_states(n, s) for n, s in ((n_tr, 31), (n_va, 32), (n_te, 33)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y_tr, y_va, y_te = lab.labels(q_tr), lab.labels(q_va), lab.labels(q_te)
+    torch.cuda.synchronize()
+    t_lab = time.perf_counter() - t0
+    n_lab = n_tr + n_va + n_te
+    dev_q = lambda a: torch.from_numpy(a.astype(np.float32)).to(lab.dev)
+    sur = Surrogate(lab.dev, seed=0, batch=4096)
+    log(f"[bench] surrogate: training {args.surrogate_epochs} epochs")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = sur.train(dev_q(q_tr), y_tr, epochs=args.surrogate_epochs, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = args.surrogate_epochs * (n_tr // 4096)
+    eps = float((sur.predict(dev_q(q_va)) - y_va).abs().max().item())
+    radii = torch.from_numpy(st.sphere_radii).to(lab.dev)
+    p_te = sur.predict(dev_q(q_te))
+    need, _ = sur.fallback(p_te, radii, vox, margin, eps)
+    need = need.cpu().numpy().astype(bool)
+    exact_clear = y_te.cpu().numpy().astype(np.float64) * vox - st.sphere_radii[None, :]
+    near = (exact_clear < margin).any(1)
+    misses = int((near & ~need).sum())
+    res = {"workload": "128^3 self-map at 1 cm, obstacle links 0-1, 12 spheres on links 4-7; "
+                       "MLP 14-256-256-256-12, BF16 MFMA, FP32 accumulate, Adam",
+           "train_states": n_tr, "val_states": n_va, "test_states": n_te,
+           "label_states_per_s": n_lab / t_lab,
+           "label_edt_mvox_s": n_lab * st.grid.n / t_lab / 1e6,
+           "train_ms_per_step": 1e3 * t_train / max(1, steps), "loss_first": hist[0],
+           "loss_last": hist[-1], "eps_max_vox": eps, "margin_m": margin,
+           "test_fallback_rate": float(need.mean()), "test_truly_within_margin": float(near.mean()),
+           "test_misses": misses}
+
+    # inference batch of 4096 look-ahead states: exact only vs surrogate + fallback
+    B = 4096
+    qb = inputs.random_joint_states(B, 34)
+    poses, cen = lab.stage(qb)
+    qd = dev_q(qb)
+    out = torch.empty((B, 12), dtype=torch.float32, device=lab.dev)
+
+    def exact_all():
+        lab.distances(poses, cen, out)
+
+    def assisted():
+        sur.predict(qd, out)
+        nd, _ = sur.fallback(out, radii, vox, margin, eps)
+        idx = torch.nonzero(nd, as_tuple=True)[0]
+        if idx.numel():
+            out[idx] = lab.distances(poses[idx], cen[idx])
+
+    for fn in (exact_all, assisted):
+        fn()
+    torch.cuda.synchronize()
+
+    def clock(fn, reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / reps
+
+    res["batch4096_exact_ms"] = clock(exact_all, 3)
+    res["batch4096_assisted_ms"] = clock(assisted, 3)
+    res["batch4096_speedup"] = res["batch4096_exact_ms"] / res["batch4096_assisted_ms"]
+
+    # per control cycle: 16 look-ahead states, latency to results on the host
+    S = 16
+    lab16 = SelfMapLabeler(st, chunk=S)
+    qs = inputs.random_joint_states(S * args.lookahead_cycles, 35)
+    p16, c16 = lab16.stage(qs)
+    q16 = dev_q(qs)
+    o16 = torch.empty((S, 12), dtype=torch.float32, device=lab.dev)
+    host = torch.empty((S, 12), dtype=torch.float32, pin_memory=True)
+    st_ = torch.cuda.current_stream()
+
+    def lat(fn, n):
+        xs = []
+        for k in range(n):
+            t = time.perf_counter()
+            fn(k)
+            host.copy_(o16, non_blocking=True)
+            st_.synchronize()
+            xs.append(1e3 * (time.perf_counter() - t))
+        return {"p50_ms": pct(xs, 50), "p99_ms": pct(xs, 99), "cycles": n}
+
+    def cyc_exact(k):
+        lab16.distances(p16[k * S:(k + 1) * S], c16[k * S:(k + 1) * S], o16)
+
+    def cyc_assisted(k):
+        sur.predict(q16[k * S:(k + 1) * S], o16)
+        nd, cnt = sur.fallback(o16, radii, vox, margin, eps)
+        if int(cnt.item()):
+            idx = torch.nonzero(nd, as_tuple=True)[0] + k * S
+            o16[idx - k * S] = lab16.distances(p16[idx], c16[idx])
+
+    n = args.lookahead_cycles
+    res["lookahead16_exact"] = lat(cyc_exact, n)
+    res["lookahead16_assisted"] = lat(cyc_assisted, n)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +296,10 @@ def main():
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--batch-maps", type=int, default=32, help="0 = skip the batched workload")
     ap.add_argument("--batch-cycles", type=int, default=1000)
+    ap.add_argument("--surrogate-train", type=int, default=262144,
+                    help="training states of the surrogate (0 = skip the surrogate workload)")
+    ap.add_argument("--surrogate-epochs", type=int, default=30)
+    ap.add_argument("--lookahead-cycles", type=int, default=1000)
     ap.add_argument("--states", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -300,6 +422,10 @@ def main():
     if args.batch_maps > 0:
         batched = batched_workload(args, torch, edt, inputs, host_latency=True)
 
+    surrogate = None
+    if args.surrogate_train > 0:
+        surrogate = surrogate_workload(args, torch, inputs)
+
     out = {"metric": METRIC, "value": value, "unit": "Mvoxels/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
@@ -312,7 +438,7 @@ def main():
                       "points_per_frame": int(ci.frames[0].shape[0]),
                       "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
            "latency": latency, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
-           "batched": batched,
+           "batched": batched, "surrogate": surrogate,
            "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",
                              "workload": "live camera scene, 256x256x128 at 1 cm"}}
     if not args.no_cpu_baseline:

@@ -92,15 +92,17 @@ def test_forward_matches_oracle(batch):
     outs = [acts["h1"][:batch], acts["h2"][:batch], acts["h3"][:batch], acts["y"][:batch, :12]]
     for li, (W, b) in enumerate(params):
         z = M.f32(ins[li] @ W.T + b)
+        # float32 summation of n products: error <= (n + 2) 2^-24 sum |terms|
+        acc = (np.abs(ins[li]) @ np.abs(W).T + np.abs(b)) * (W.shape[1] + 2) * 2.0 ** -24
+        got = outs[li]
         if li < 3:
             ref = M.bf16(np.maximum(z, 0))
-            got = outs[li]
-            step = np.maximum(np.abs(ref), 1e-30) * 2 ** -7
-            assert (np.abs(got - ref) <= step).all(), li
+            # plus one bf16 step of the result when the sums straddle a boundary
+            allowed = 2.0 ** -7 * np.maximum(np.abs(ref), np.abs(got)) + 2 * acc
+            assert (np.abs(got - ref) <= allowed).all(), (li, np.abs(got - ref).max())
             assert np.mean(got == ref) > 0.995, li
         else:
-            got = outs[li]
-            assert np.allclose(got, z, rtol=1e-5, atol=1e-5 * np.abs(z).max())
+            assert (np.abs(got - z) <= 2 * acc + 1e-30).all(), (li, np.abs(got - z).max())
     assert np.array_equal(y.cpu().numpy(), acts["y"][:batch, :12].astype(np.float32))
     # end to end from q: small relative to the output scale
     y_ref, _ = M.forward(params, q_np.astype(np.float64))
