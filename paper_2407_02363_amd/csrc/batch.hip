@@ -252,6 +252,7 @@ int batch_common(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t w
     if (tuning) {
         t.xy_tw = tuning->xy_tile;
         t.z_tw = tuning->z_tile;
+        t.z_nt = 256;
     } else {
         t = batch_current(n_maps, nx, ny, nz);
     }
@@ -323,7 +324,7 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
     const int XY[] = {16, 32};
     const int Z[] = {16, 32, 64};
     float best_ms = 1e30f;
-    EdtTuning bt{0, 0};
+    EdtTuning bt{0, 0, 256};
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
         set_error("edt_autotune_batched: hipEventCreate failed");
@@ -332,7 +333,7 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
     int rc = EDT_OK;
     for (int txy : XY) {
         for (int tz : Z) {
-            edt_tuning_t cand{txy, tz};
+            edt_tuning_t cand{txy, tz, 256};
             BatchPlan p;
             EdtTuning t;
             rc = batch_common(maps, n_maps, ws, ws_bytes, &cand, p, t);
@@ -359,7 +360,7 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
             if (rc) break;
             if (total / reps < best_ms) {
                 best_ms = total / reps;
-                bt = EdtTuning{txy, tz};
+                bt = EdtTuning{txy, tz, 256};
             }
         }
         if (rc) break;
@@ -384,12 +385,13 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
     if (best) {
         best->xy_tile = bt.xy_tw;
         best->z_tile = bt.z_tw;
+        best->z_group = 256;
     }
     if (best_us) *best_us = 1000.0f * best_ms;
     // leave the chosen tiling's result in the outputs
     BatchPlan p;
     EdtTuning t;
-    edt_tuning_t chosen{bt.xy_tw, bt.z_tw};
+    edt_tuning_t chosen{bt.xy_tw, bt.z_tw, 256};
     rc = batch_common(maps, n_maps, ws, ws_bytes, &chosen, p, t);
     if (!rc) rc = launch_batched(p, bt.xy_tw, bt.z_tw, static_cast<unsigned*>(ws), st);
     if (!rc && hipStreamSynchronize(st) != hipSuccess) {

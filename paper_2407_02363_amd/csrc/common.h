@@ -42,13 +42,14 @@ inline int check_launch(const char* what)
 struct EdtTuning {
     int xy_tw;
     int z_tw;
+    int z_nt;   // threads per z work-group (64, 128 or 256)
 };
 EdtTuning default_tuning(const edt_grid_t* g);   // heuristic
 EdtTuning current_tuning(const edt_grid_t* g);   // autotuned if cached, else heuristic
-bool tile_ok(int pass, int tw, const edt_grid_t* g);   // pass 1 = xy, 2 = z
+bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt);   // pass 1 = xy, 2 = z
 bool needs_wide(const edt_grid_t* g);
 int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st);
-int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, hipStream_t st);
+int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st);
 
 // Work-group index remap so that consecutive logical tiles land on the same
 // XCD (the dispatcher deals work-groups to the 8 XCDs round-robin).  A

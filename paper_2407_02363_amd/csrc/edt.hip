@@ -345,12 +345,13 @@ int edt_compute_stage(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, i
     if (tuning) {
         t.xy_tw = tuning->xy_tile;
         t.z_tw = tuning->z_tile;
+        t.z_nt = tuning->z_group ? tuning->z_group : 256;
     } else {
         t = current_tuning(grid);
     }
-    if (!tile_ok(1, t.xy_tw, grid) || !tile_ok(2, t.z_tw, grid)) {
-        set_error("tiles (%d, %d) not valid for a %d x %d x %d grid", t.xy_tw, t.z_tw, grid->nx,
-                  grid->ny, grid->nz);
+    if (!tile_ok(1, t.xy_tw, grid, 256) || !tile_ok(2, t.z_tw, grid, t.z_nt)) {
+        set_error("tiles (%d, %d / %d) not valid for a %d x %d x %d grid", t.xy_tw, t.z_tw, t.z_nt,
+                  grid->nx, grid->ny, grid->nz);
         return EDT_ERR_UNSUPPORTED;
     }
     const hipStream_t st = as_stream(stream);
@@ -358,7 +359,7 @@ int edt_compute_stage(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, i
         rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, st);
         if (rc) return rc;
     }
-    if (stage & EDT_STAGE_Z) rc = launch_edt_z(grid, d2, site, t.z_tw, st);
+    if (stage & EDT_STAGE_Z) rc = launch_edt_z(grid, d2, site, t.z_tw, t.z_nt, st);
     return rc;
 }
 

@@ -390,9 +390,9 @@ constexpr int XSTAGE_WORDS = 1024;
 
 // Dynamic LDS of k_edt_xy: envelope entries (or the row staging buffer,
 // whichever is larger) plus three row-record arrays.
-__host__ __device__ inline size_t z_lds(int tw, int nzv)
+__host__ __device__ inline size_t z_lds(int tw, int nzv, int nt = NT)
 {
-    return (size_t)4 * NT * ((nzv + NT / tw - 1) / (NT / tw));
+    return (size_t)4 * nt * ((nzv + nt / tw - 1) / (nt / tw));
 }
 
 __host__ __device__ inline size_t xy_lds(int tw, int nyv)
@@ -577,11 +577,11 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
 // step 4 per (row, column tile)
 // ---------------------------------------------------------------------------
 // One z tile: row y, columns [x0, x0 + TW), all z; T = y * ntx + x0 / TW.
-template <int TW, bool WIDE>
+template <int TW, bool WIDE, int NTZ = NT>
 __device__ __forceinline__ void edt_z_tile(int32_t* d2, int32_t* site, int nx, int ny, int nz,
                                            int ntx, int T, uint32_t* lds)
 {
-    constexpr int NB = NT / TW;
+    constexpr int NB = NTZ / TW;
     constexpr int CH = 8;   // positions per software-pipelined chunk
     const int L = (nz + NB - 1) / NB;
     uint32_t* ent = lds;    // [NB*L][TW]

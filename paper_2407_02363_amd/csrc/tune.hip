@@ -18,10 +18,11 @@ std::map<std::tuple<int, int, int>, EdtTuning> g_tuned;
 
 const int XY_TILES[] = {16, 32, 64};
 const int Z_TILES[] = {8, 16, 32, 64};
+const int Z_GROUPS[] = {64, 128, 256};
 
 // Average time (ms) of `reps` launches of one pass with tile tw.
 int time_pass(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, int32_t* site, int pass,
-              int tw, int reps, hipStream_t st, float* ms)
+              int tw, int nt, int reps, hipStream_t st, float* ms)
 {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -38,7 +39,7 @@ int time_pass(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, int32_t* sit
         if (rc) break;
         (void)hipEventRecord(a, st);
         rc = pass == 1 ? launch_edt_xy(g, occ, reinterpret_cast<uint32_t*>(site), tw, st)
-                       : launch_edt_z(g, d2, site, tw, st);
+                       : launch_edt_z(g, d2, site, tw, nt, st);
         (void)hipEventRecord(b, st);
         if (rc) break;
         if (hipEventSynchronize(b) != hipSuccess) {
@@ -81,6 +82,7 @@ int edt_default_tuning(const edt_grid_t* grid, edt_tuning_t* out)
     const EdtTuning t = current_tuning(grid);
     out->xy_tile = t.xy_tw;
     out->z_tile = t.z_tw;
+    out->z_group = t.z_nt;
     return EDT_OK;
 }
 
@@ -95,20 +97,22 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
     }
     const hipStream_t st = as_stream(stream);
     float best_xy = 1e30f, best_z = 1e30f;
-    int bxy = 0, bz = 0;
+    int bxy = 0, bz = 0, bnt = 0;
     for (int tw : XY_TILES) {
-        if (!tile_ok(1, tw, grid)) continue;
+        if (!tile_ok(1, tw, grid, 256)) continue;
         float ms = 0.0f;
-        rc = time_pass(grid, occ, d2, site, 1, tw, reps, st, &ms);
+        rc = time_pass(grid, occ, d2, site, 1, tw, 256, reps, st, &ms);
         if (rc) return rc;
         if (ms < best_xy) { best_xy = ms; bxy = tw; }
     }
-    for (int tw : Z_TILES) {
-        if (!tile_ok(2, tw, grid)) continue;
-        float ms = 0.0f;
-        rc = time_pass(grid, occ, d2, site, 2, tw, reps, st, &ms);
-        if (rc) return rc;
-        if (ms < best_z) { best_z = ms; bz = tw; }
+    for (int nt : Z_GROUPS) {
+        for (int tw : Z_TILES) {
+            if (!tile_ok(2, tw, grid, nt)) continue;
+            float ms = 0.0f;
+            rc = time_pass(grid, occ, d2, site, 2, tw, nt, reps, st, &ms);
+            if (rc) return rc;
+            if (ms < best_z) { best_z = ms; bz = tw; bnt = nt; }
+        }
     }
     if (!bxy || !bz) {
         set_error("edt_autotune: no valid tile for this grid");
@@ -116,11 +120,11 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz};
+        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz, bnt};
     }
     // leave a complete transform in d2 / site
     rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), bxy, st);
-    if (!rc) rc = launch_edt_z(grid, d2, site, bz, st);
+    if (!rc) rc = launch_edt_z(grid, d2, site, bz, bnt, st);
     if (rc) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) {
         set_error("edt_autotune: stream synchronisation failed");
@@ -129,6 +133,7 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
     if (best) {
         best->xy_tile = bxy;
         best->z_tile = bz;
+        best->z_group = bnt;
     }
     if (best_us) *best_us = 1000.0f * (best_xy + best_z);
     return EDT_OK;

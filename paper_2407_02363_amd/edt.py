@@ -41,7 +41,7 @@ class SphereResult(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("xy_tile", ctypes.c_int32), ("z_tile", ctypes.c_int32)]
+    _fields_ = [("xy_tile", ctypes.c_int32), ("z_tile", ctypes.c_int32), ("z_group", ctypes.c_int32)]
 
 
 class BatchMap(ctypes.Structure):
@@ -195,7 +195,7 @@ def _tuning(t):
         return None
     if isinstance(t, Tuning):
         return ctypes.byref(t)
-    return ctypes.byref(Tuning(int(t[0]), int(t[1])))
+    return ctypes.byref(Tuning(int(t[0]), int(t[1]), int(t[2]) if len(t) > 2 else 0))
 
 
 def edt_compute_stage(grid, occ, d2, site, stage: int, tuning=None, stream=None):
@@ -222,11 +222,11 @@ def edt_default_tuning(grid):
     g = make_grid(grid)
     t = Tuning()
     _check(lib().edt_default_tuning(ctypes.byref(g), ctypes.byref(t)), "edt_default_tuning")
-    return (t.xy_tile, t.z_tile)
+    return (t.xy_tile, t.z_tile, t.z_group)
 
 
 def edt_autotune(grid, occ, d2, site, reps: int = 10, stream=None):
-    """Returns ((xy_tile, z_tile), microseconds of one transform)."""
+    """Returns ((xy_tile, z_tile, z_group), microseconds of one transform)."""
     g = make_grid(grid)
     n = _n(g)
     t = Tuning()
@@ -235,7 +235,7 @@ def edt_autotune(grid, occ, d2, site, reps: int = 10, stream=None):
                               _dev(d2, torch.int32, "d2", n), _dev(site, torch.int32, "site", n),
                               int(reps), ctypes.byref(t), ctypes.byref(us), _stream(stream)),
            "edt_autotune")
-    return (t.xy_tile, t.z_tile), float(us.value)
+    return (t.xy_tile, t.z_tile, t.z_group), float(us.value)
 
 
 def edt_query_spheres(grid, d2, site, centres, radii, out, stream=None):

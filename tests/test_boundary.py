@@ -80,10 +80,12 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.edt_query_spheres(ctypes.byref(ok), None, None, None, None, 0, None, None) == 0
     assert lib.edt_workspace_bytes(ctypes.byref(ok)) == 0
     # tuning: defaults are valid tiles; bad tiles are rejected before launch
+    one = ctypes.c_void_p(256)
     t = edt.Tuning()
     assert lib.edt_default_tuning(ctypes.byref(ok), ctypes.byref(t)) == 0
-    assert t.xy_tile in (16, 32, 64) and t.z_tile in (8, 16, 32, 64)
-    one = ctypes.c_void_p(256)
+    assert t.xy_tile in (16, 32, 64) and t.z_tile in (8, 16, 32, 64) and t.z_group in (64, 128, 256)
+    assert lib.edt_compute_tuned(ctypes.byref(ok), one, one, one, ctypes.byref(edt.Tuning(32, 64, 32)),
+                                 None) == -5
     bad_t = edt.Tuning(24, 8)
     assert lib.edt_compute_tuned(ctypes.byref(ok), one, one, one, ctypes.byref(bad_t), None) == -5
     huge = edt.EdtGrid(8, 1024, 8, (ctypes.c_float * 3)(0, 0, 0), 0.01)

@@ -115,19 +115,21 @@ def test_every_tiling_is_identical(oracle_lib, shape):
     o = torch.from_numpy(occ.ravel()).to(dev())
     d2 = torch.empty(occ.size, dtype=torch.int32, device=dev())
     site = torch.empty_like(d2)
-    for xt in (16, 32, 64):
-        for zt in (8, 16, 32, 64):
-            say(f"[tiling] {shape} xy={xt} z={zt}")
+    combos = [(xt, zt, 256) for xt in (16, 32, 64) for zt in (8, 16, 32, 64)]
+    combos += [(32, zt, zg) for zg in (64, 128) for zt in (8, 16, 32, 64) if zt <= zg]
+    for xt, zt, zg in combos:
+        if True:
+            say(f"[tiling] {shape} xy={xt} z={zt}/{zg}")
             d2.fill_(-7)
             site.fill_(-7)
             try:
-                edt.edt_compute_tuned(g, o, d2, site, (xt, zt))
+                edt.edt_compute_tuned(g, o, d2, site, (xt, zt, zg))
             except edt.EdtError as e:
                 assert e.status == -5   # tile needs more LDS than the device has
                 continue
             torch.cuda.synchronize()
-            assert np.array_equal(d2.cpu().numpy().reshape(shape), rd2), (xt, zt)
-            assert np.array_equal(site.cpu().numpy().reshape(shape), rsite), (xt, zt)
+            assert np.array_equal(d2.cpu().numpy().reshape(shape), rd2), (xt, zt, zg)
+            assert np.array_equal(site.cpu().numpy().reshape(shape), rsite), (xt, zt, zg)
 
 
 def test_autotune_keeps_results(oracle_lib):
@@ -139,9 +141,9 @@ def test_autotune_keeps_results(oracle_lib):
     o = torch.from_numpy(occ.ravel()).to(dev())
     d2 = torch.empty(occ.size, dtype=torch.int32, device=dev())
     site = torch.empty_like(d2)
-    (xt, zt), us = edt.edt_autotune(g, o, d2, site, reps=3)
-    say(f"[autotune] 64^3 -> xy={xt} z={zt} {us:.1f} us")
-    assert us > 0 and edt.edt_default_tuning(g) == (xt, zt)
+    tiles, us = edt.edt_autotune(g, o, d2, site, reps=3)
+    say(f"[autotune] 64^3 -> {tiles} {us:.1f} us")
+    assert us > 0 and edt.edt_default_tuning(g) == tiles
     rd2, rsite = oracle_lib.edt(occ)
     assert np.array_equal(d2.cpu().numpy().reshape(occ.shape), rd2)
     d2.fill_(0)
