@@ -9,7 +9,9 @@ in both.  Inputs are resident in device memory before timing starts.
 
 Printed as one JSON line:
   value        EDT voxels per second over whole cycles (2 maps per cycle),
-               in Mvoxels/s -- insert, clear and query time included.
+               in Mvoxels/s -- insert, clear and query time included; each
+               cycle is one HIP-graph replay (timing "graph"; the eager
+               rate, one library call per step, is under "eager").
   latency      p50 / p99 of the per-cycle latency over >= 1000 cycles, host
                clock from enqueue to the sphere results landing in host
                memory, plain per-map launches and graph-replayed cycles.
@@ -185,29 +187,33 @@ def surrogate_workload(args, torch, inputs):
     t_lab = time.perf_counter() - t0
     n_lab = n_tr + n_va + n_te
     dev_q = lambda a: torch.from_numpy(a.astype(np.float32)).to(lab.dev)
-    sur = Surrogate(lab.dev, seed=0, batch=4096)
+    sur = Surrogate(lab.dev, seed=0, batch=4096, clip_vox=24.0)
     log(f"[bench] surrogate: training {args.surrogate_epochs} epochs")
+    qd_tr = dev_q(q_tr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = sur.train(dev_q(q_tr), y_tr, epochs=args.surrogate_epochs, lr=2e-3, seed=0)
+    hist = sur.train(qd_tr, y_tr, epochs=args.surrogate_epochs, lr=2e-3, seed=0, lr_final=2e-5)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     steps = args.surrogate_epochs * (n_tr // 4096)
-    eps = float((sur.predict(dev_q(q_va)) - y_va).abs().max().item())
+    eps = sur.calibrate(dev_q(q_va), y_va).cpu().numpy()
+    err_va = (sur.predict(dev_q(q_va)) - y_va.clamp(max=sur.clip_vox)).abs().max().item()
     radii = torch.from_numpy(st.sphere_radii).to(lab.dev)
     p_te = sur.predict(dev_q(q_te))
-    need, _ = sur.fallback(p_te, radii, vox, margin, eps)
+    need, _ = sur.fallback(p_te, radii, vox, margin)
     need = need.cpu().numpy().astype(bool)
     exact_clear = y_te.cpu().numpy().astype(np.float64) * vox - st.sphere_radii[None, :]
     near = (exact_clear < margin).any(1)
     misses = int((near & ~need).sum())
     res = {"workload": "128^3 self-map at 1 cm, obstacle links 0-1, 12 spheres on links 4-7; "
-                       "MLP 14-256-256-256-12, BF16 MFMA, FP32 accumulate, Adam",
+                       "MLP 14-256-256-256-12, BF16 MFMA, FP32 accumulate, Adam with a cosine "
+                       "step size, distances clipped at 24 voxels",
            "train_states": n_tr, "val_states": n_va, "test_states": n_te,
            "label_states_per_s": n_lab / t_lab,
            "label_edt_mvox_s": n_lab * st.grid.n / t_lab / 1e6,
            "train_ms_per_step": 1e3 * t_train / max(1, steps), "loss_first": hist[0],
-           "loss_last": hist[-1], "eps_max_vox": eps, "margin_m": margin,
+           "loss_last": hist[-1], "eps_vox_per_sphere": [round(float(e), 3) for e in eps],
+           "eps_max_vox": float(eps.max()), "val_abs_err_max_vox": err_va, "margin_m": margin,
            "test_fallback_rate": float(need.mean()), "test_truly_within_margin": float(near.mean()),
            "test_misses": misses}
 
@@ -223,7 +229,7 @@ def surrogate_workload(args, torch, inputs):
 
     def assisted():
         sur.predict(qd, out)
-        nd, _ = sur.fallback(out, radii, vox, margin, eps)
+        nd, _ = sur.fallback(out, radii, vox, margin)
         idx = torch.nonzero(nd, as_tuple=True)[0]
         if idx.numel():
             out[idx] = lab.distances(poses[idx], cen[idx])
@@ -269,7 +275,7 @@ def surrogate_workload(args, torch, inputs):
 
     def cyc_assisted(k):
         sur.predict(q16[k * S:(k + 1) * S], o16)
-        nd, cnt = sur.fallback(o16, radii, vox, margin, eps)
+        nd, cnt = sur.fallback(o16, radii, vox, margin)
         if int(cnt.item()):
             idx = torch.nonzero(nd, as_tuple=True)[0] + k * S
             o16[idx - k * S] = lab16.distances(p16[idx], c16[idx])
@@ -298,7 +304,7 @@ def main():
     ap.add_argument("--batch-cycles", type=int, default=1000)
     ap.add_argument("--surrogate-train", type=int, default=262144,
                     help="training states of the surrogate (0 = skip the surrogate workload)")
-    ap.add_argument("--surrogate-epochs", type=int, default=30)
+    ap.add_argument("--surrogate-epochs", type=int, default=60)
     ap.add_argument("--lookahead-cycles", type=int, default=1000)
     ap.add_argument("--states", type=int, default=64)
     args = ap.parse_args()
@@ -336,14 +342,41 @@ def main():
         cyc.run(k)
     torch.cuda.synchronize()
 
-    # ---- throughput: K cycles back to back
-    log(f"[bench] timing {args.steps} cycles")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        cyc.run(k)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    def run_steps(fn, n):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(n):
+            fn(k)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    # ---- throughput: K cycles back to back, eager (one library call per step
+    # of the cycle) and replayed from HIP graphs (one replay per cycle)
+    log(f"[bench] timing {args.steps} eager cycles")
+    el_eager = run_steps(cyc.run, args.steps)
+    eager = {"ms_per_cycle": 1e3 * el_eager / args.steps,
+             "mvox_s": cyc.voxels_per_cycle * args.steps / el_eager / 1e6}
+    graphs = None
+    if args.graphs > 0:
+        log(f"[bench] capturing {args.graphs} cycle graphs")
+        graphs = cyc.capture_graphs(args.graphs)
+        # check the replayed cycle against an eager run of the same slot
+        cyc.run(1)
+        torch.cuda.synchronize()
+        ref = (cyc.d2_env.clone(), cyc.site_env.clone(), cyc.out_env.clone(), cyc.out_self.clone())
+        graphs[1].replay()
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, b) for a, b in
+                   zip(ref, (cyc.d2_env, cyc.site_env, cyc.out_env, cyc.out_self)))
+        if not same:
+            raise SystemExit("graph replay differs from the eager cycle")
+        for k in range(args.warmup):
+            graphs[k % len(graphs)].replay()
+        log(f"[bench] timing {args.steps} graph-replayed cycles")
+        el = run_steps(lambda k: graphs[k % len(graphs)].replay(), args.steps)
+        mode = "graph"
+    else:
+        el, mode = el_eager, "eager"
     ms_per_step = 1e3 * el / args.steps
     value = cyc.voxels_per_cycle * args.steps / el / 1e6
 
@@ -366,32 +399,31 @@ def main():
     lat_plain = latency_run(cyc.run, args.latency_cycles)
     latency = {"plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
                          "cycles": len(lat_plain)}}
-    if args.graphs > 0:
-        log(f"[bench] capturing {args.graphs} cycle graphs")
-        graphs = cyc.capture_graphs(args.graphs)
-        # check the replayed cycle against an eager run of the same slot
-        cyc.run(1)
-        torch.cuda.synchronize()
-        ref = (cyc.d2_env.clone(), cyc.site_env.clone(), cyc.out_env.clone(), cyc.out_self.clone())
-        graphs[1].replay()
-        torch.cuda.synchronize()
-        same = all(torch.equal(a, b) for a, b in
-                   zip(ref, (cyc.d2_env, cyc.site_env, cyc.out_env, cyc.out_self)))
-        if not same:
-            raise SystemExit("graph replay differs from the eager cycle")
-        for k in range(args.warmup):
-            graphs[k % len(graphs)].replay()
+    if graphs is not None:
         lat_graph = latency_run(lambda k: graphs[k % len(graphs)].replay(), args.latency_cycles)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            graphs[k % len(graphs)].replay()
-        torch.cuda.synchronize()
-        el_g = time.perf_counter() - t0
         latency["graph"] = {"p50_ms": pct(lat_graph, 50), "p99_ms": pct(lat_graph, 99),
-                            "cycles": len(lat_graph),
-                            "throughput_mvox_s": cyc.voxels_per_cycle * args.steps / el_g / 1e6,
-                            "ms_per_cycle": 1e3 * el_g / args.steps}
+                            "cycles": len(lat_graph)}
+
+    # ---- the same cycle with both EDTs in one persistent batched launch
+    log("[bench] cycle with the two-map batched EDT")
+    cyc_b = ControlCycle(ci, dev, batched_edt=True)
+    for k in range(args.warmup):
+        cyc_b.run(k)
+    cyc_b.run(1)
+    cyc.run(1)
+    torch.cuda.synchronize()
+    if not (torch.equal(cyc_b.d2_env, cyc.d2_env) and torch.equal(cyc_b.site_self, cyc.site_self)
+            and torch.equal(cyc_b.out_env, cyc.out_env)):
+        raise SystemExit("batched-EDT cycle differs from the per-map cycle")
+    el_b = run_steps(cyc_b.run, args.steps)
+    cycle_batched = {"eager_ms_per_cycle": 1e3 * el_b / args.steps}
+    if args.graphs > 0:
+        graphs_b = cyc_b.capture_graphs(args.graphs)
+        el_bg = run_steps(lambda k: graphs_b[k % len(graphs_b)].replay(), args.steps)
+        cycle_batched.update({"graph_ms_per_cycle": 1e3 * el_bg / args.steps,
+                              "graph_mvox_s": cyc_b.voxels_per_cycle * args.steps / el_bg / 1e6})
+        del graphs_b
+    del cyc_b
 
     # ---- per-kernel timing and roofline on the environment map
     log("[bench] per-kernel timing")
@@ -437,7 +469,8 @@ def main():
                       "grid": [g.nx, g.ny, g.nz], "maps_per_cycle": 2,
                       "points_per_frame": int(ci.frames[0].shape[0]),
                       "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
-           "latency": latency, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
+           "timing": mode, "eager": eager, "latency": latency,
+           "cycle_batched_edt": cycle_batched, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
            "batched": batched, "surrogate": surrogate,
            "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",
                              "workload": "live camera scene, 256x256x128 at 1 cm"}}

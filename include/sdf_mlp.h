@@ -7,8 +7,8 @@
  * most look-ahead states skip the exact self-map EDT.  The paper has no
  * such network: the exact self-map EDT (edt.h) produces its training labels,
  * stays the fallback for every state whose prediction lies within the
- * safety margin plus the network's measured maximum error, and is the judge
- * of that error.
+ * safety margin plus the network's measured error bound (per sphere, from
+ * held-out states: sdf_mlp_calibrate), and is the judge of that error.
  *
  * Network: input [sin q1, cos q1, ..., sin q7, cos q7] -> 256 -> 256 -> 256
  * -> 12, ReLU between layers.  BF16 inputs, weights and hidden activations
@@ -55,7 +55,7 @@ enum {
 };
 
 /* Workspace bytes for a batch (encoded inputs, saved activations, outputs,
- * gradients of the backward pass, loss partial sums). */
+ * gradients of the backward pass, loss and weight-gradient partial sums). */
 size_t sdf_mlp_workspace_bytes(int32_t batch);
 
 /* w16 = bfloat16(master), element by element (round to nearest even). */
@@ -65,25 +65,38 @@ int sdf_mlp_pack(const float* master, uint16_t* w16, void* stream);
  * sdf_mlp_forward -- predicted distances for `batch` joint states.
  *   w16     bfloat16 parameter block (weights read from it)
  *   master  float32 parameter block (biases read from it)
- *   q       float32 [batch][7] joint angles, radians
+ *   q       float32 [n_rows][7] joint angles, radians
+ *   idx     int32 [batch] (nullable): row b of the batch is state q[idx[b]]
+ *           (a minibatch gathered inside the kernel); NULL = rows 0..batch-1,
+ *           which needs n_rows >= batch.  An index outside [0, n_rows)
+ *           gives that row NaN inputs (so NaN outputs) instead of a read
+ *           outside q.
  *   y       float32 [batch][12] out, voxels (NULL: keep only in ws)
  * Saves the encoded inputs and hidden activations in ws for
  * sdf_mlp_backward.
  */
-int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, int32_t batch,
-                    float* y, void* ws, size_t ws_bytes, void* stream);
+int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, int32_t n_rows,
+                    const int32_t* idx, int32_t batch, float* y, void* ws, size_t ws_bytes,
+                    void* stream);
 
 /*
  * sdf_mlp_backward -- gradients of the mean squared error of the last
- * sdf_mlp_forward on ws against target (float32 [batch][12]).
- *   grad  float32 parameter-block layout, fully overwritten.
- *   loss  float32 device scalar out (nullable): the mean squared error.
+ * sdf_mlp_forward on ws against the targets.
+ *   target    float32 [n_rows][12], voxels; row b of the batch uses
+ *             target[idx[b]] (idx as in sdf_mlp_forward, the same array).
+ *   clip_vox  > 0: every target is first replaced by min(target, clip_vox)
+ *             (the network then learns the distance saturated at clip_vox);
+ *             <= 0: no clipping.
+ *   grad      float32 parameter-block layout, fully overwritten.
+ *   loss      float32 device scalar out (nullable): the mean squared error.
  * dY and every masked upstream gradient are rounded to bfloat16 before
- * they enter a matrix product; weight gradients reduce over the batch in a
- * fixed order (no atomics), so two runs give identical bits.
+ * they enter a matrix product.  Weight and bias gradients reduce over the
+ * batch in fixed-size chunks whose partial sums are added in chunk order
+ * (no atomics), so two runs give identical bits.
  */
-int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t batch, float* grad,
-                     float* loss, void* ws, size_t ws_bytes, void* stream);
+int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t n_rows, const int32_t* idx,
+                     int32_t batch, float clip_vox, float* grad, float* loss, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /*
  * sdf_mlp_adam -- one Adam step (bias-corrected; step counts from 1) on
@@ -96,13 +109,34 @@ int sdf_mlp_adam(float* master, uint16_t* w16, float* m, float* v, const float* 
 /*
  * sdf_mlp_fallback -- the exact-EDT fallback rule.  State b needs the exact
  * self-map transform when some sphere i has predicted clearance
- * y[b][i] * voxel - radii[i] below margin + eps_vox * voxel (metres), i.e.
- * within the safety margin once the surrogate's worst error is allowed for.
+ * y[b][i] * voxel - radii[i] below margin + eps_vox[i] * voxel (metres),
+ * i.e. within the safety margin once the surrogate's error bound for that
+ * sphere is allowed for; a NaN prediction always needs it.  Evaluated in
+ * float32 in exactly that order: c = y * voxel - r, t = margin +
+ * eps * voxel, exact iff !(c >= t).
+ *   radii, eps_vox  float32 [12] device arrays (metres, voxels).
  *   need   int32 [batch] out: 1 = run the exact EDT for this state.
  *   count  int32 device scalar out: number of such states.
  */
-int sdf_mlp_fallback(const float* y, const float* radii, int32_t batch, float voxel, float margin,
-                     float eps_vox, int32_t* need, int32_t* count, void* stream);
+int sdf_mlp_fallback(const float* y, const float* radii, const float* eps_vox, int32_t batch,
+                     float voxel, float margin, int32_t* need, int32_t* count, void* stream);
+
+/*
+ * sdf_mlp_calibrate -- the error bound the fallback rule allows for, from
+ * held-out states with exact labels.  For every sphere i:
+ *   eps_vox[i] = max(0, max over rows b with target[b][i] < clip_vox of
+ *                pred[b][i] - target[b][i])        (float32 difference)
+ * i.e. the largest overestimate of the distance on the held-out rows whose
+ * exact distance lies below the clip (clip_vox <= 0: every row).  Only an
+ * overestimate can hide a sphere inside the margin, and a sphere inside the
+ * margin has an exact distance below the clip as long as
+ * (margin + radius) / voxel + eps < clip_vox.  A NaN prediction makes the
+ * bound +inf.
+ *   pred, target  float32 [batch][12] device (voxels); eps_vox float32 [12]
+ *   device out, fully overwritten.
+ */
+int sdf_mlp_calibrate(const float* pred, const float* target, int32_t batch, float clip_vox,
+                      float* eps_vox, void* stream);
 
 #ifdef __cplusplus
 }

@@ -70,8 +70,12 @@ def forward(params, q, rounding=True):
     return y, acts
 
 
-def loss_and_dy(y, target, rounding=True):
-    """MSE over every output; dY = 2 (y - t) / (B * 12)."""
+def loss_and_dy(y, target, rounding=True, clip=None):
+    """MSE over every output; dY = 2 (y - t) / (B * 12).  With clip > 0 the
+    targets are min(target, clip) first (the network learns the distance
+    saturated at clip)."""
+    if clip is not None and clip > 0:
+        target = np.minimum(target, clip)
     d = y - target
     loss = float(np.mean(d * d))
     dy = 2.0 * d / d.size
@@ -122,7 +126,37 @@ def adam(master, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 def needs_exact(pred_vox, radii_m, voxel, margin_m, eps_vox):
     """Exact-EDT fallback rule: a state needs the exact self-map transform when
     any sphere's predicted clearance, pred * voxel - r, is below the safety
-    margin plus the surrogate's measured maximum error (or is not a number)."""
-    clearance = np.asarray(pred_vox, np.float64) * voxel - np.asarray(radii_m, np.float64)[None, :]
-    # a NaN prediction is never trusted
-    return (~(clearance >= margin_m + eps_vox * voxel)).any(axis=1)
+    margin plus the surrogate's error bound for that sphere (eps_vox: one
+    number or one per sphere, voxels), or is not a number.
+
+    The rule turns floats into a yes/no, so it is evaluated in float32 with
+    one rounding per operation in this order -- c = pred * voxel - r and
+    t = margin + eps * voxel -- the precision and order of the device's
+    decision."""
+    one = np.float32
+    pred = np.asarray(pred_vox, np.float32)
+    r = np.asarray(radii_m, np.float32)[None, :]
+    eps = np.broadcast_to(np.asarray(eps_vox, np.float32), (pred.shape[1],))[None, :]
+    with np.errstate(invalid="ignore"):
+        c = pred * one(voxel) - r
+        t = one(margin_m) + eps * one(voxel)
+        # a NaN prediction is never trusted
+        return (~(c >= t)).any(axis=1)
+
+
+def calibrate(pred_vox, target_vox, clip_vox):
+    """Per-sphere error bound the fallback rule allows for: the largest
+    overestimate pred - target (float32 difference) over the held-out rows
+    whose exact target lies below clip_vox (every row if clip_vox <= 0),
+    and 0 if there is none.  Only an overestimate can hide a sphere inside
+    the margin, and such a sphere has an exact distance below the clip when
+    (margin + radius) / voxel + bound < clip_vox.  A NaN prediction on a
+    counted row makes the bound infinite."""
+    pred = np.asarray(pred_vox, np.float32)
+    tgt = np.asarray(target_vox, np.float32)
+    with np.errstate(invalid="ignore"):
+        rows = np.ones(tgt.shape, bool) if clip_vox <= 0 else (tgt < np.float32(clip_vox))
+        d = pred - tgt
+    d = np.where(np.isnan(pred), np.float32(np.inf), d)
+    d = np.where(rows, d, np.float32(0.0))
+    return np.maximum(d.max(axis=0), np.float32(0.0)).astype(np.float32)

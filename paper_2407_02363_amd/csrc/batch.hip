@@ -31,7 +31,6 @@ struct MapDesc {
     int ntx_xy, ntx_z;       // column tiles per slice / per row
     int xy_begin, xy_count;  // queue range of the map's xy tiles
     int z_begin;             // queue start of its z tiles
-    int fast;                // 16-byte row path usable
     const uint8_t* occ;
     int32_t* d2;
     int32_t* site;
@@ -52,7 +51,7 @@ __global__ void k_batch_reset(unsigned* ws, int n)
     if (i < n) ws[i] = 0u;
 }
 
-template <int TXY, int TZ, int NWMAX>
+template <int TXY, int TZ>
 __global__ __launch_bounds__(NT) void k_edt_batched(BatchArgs a, unsigned* ws, unsigned spin_limit)
 {
     extern __shared__ uint32_t lds[];
@@ -69,12 +68,7 @@ __global__ __launch_bounds__(NT) void k_edt_batched(BatchArgs a, unsigned* ws, u
             while (m + 1 < a.n_maps && a.m[m + 1].xy_begin <= it) ++m;
             const MapDesc& d = a.m[m];
             uint32_t* xy = reinterpret_cast<uint32_t*>(d.site);
-            if (d.fast)
-                edt_xy_tile<TXY, false, NWMAX, true>(d.occ, xy, d.nx, d.ny, d.nz, d.ntx_xy,
-                                                     it - d.xy_begin, lds);
-            else
-                edt_xy_tile<TXY, false, NWMAX, false>(d.occ, xy, d.nx, d.ny, d.nz, d.ntx_xy,
-                                                      it - d.xy_begin, lds);
+            edt_xy_tile<TXY, false>(d.occ, xy, d.nx, d.ny, d.nz, d.ntx_xy, it - d.xy_begin, lds);
             __syncthreads();   // every thread's stores of this tile are issued
             if (threadIdx.x == 0) {
                 __threadfence();
@@ -135,7 +129,6 @@ int make_plan(const edt_batch_map_t* maps, int n, int txy, int tz, BatchPlan& p)
         d.xy_begin = q;
         d.xy_count = g->nz * d.ntx_xy;
         q += d.xy_count;
-        d.fast = (g->nx % 64 == 0 && (reinterpret_cast<uintptr_t>(maps[i].occ) & 15) == 0) ? 1 : 0;
         d.occ = maps[i].occ;
         d.d2 = maps[i].d2;
         d.site = maps[i].site;
@@ -172,10 +165,10 @@ EdtTuning batch_current(int n, int nx, int ny, int nz)
     return it != g_batch_tuned.end() ? it->second : batch_default(nx, ny, nz);
 }
 
-template <int TXY, int TZ, int NWMAX>
-int launch_batched_t(const BatchPlan& p, unsigned* ws, hipStream_t st)
+template <int TXY, int TZ>
+int launch_batched_tz(const BatchPlan& p, unsigned* ws, hipStream_t st)
 {
-    auto kern = k_edt_batched<TXY, TZ, NWMAX>;
+    auto kern = k_edt_batched<TXY, TZ>;
     const size_t lds = std::max(xy_lds(TXY, p.ny_max), z_lds(TZ, p.nz_max));
     static bool lds_ok = false;
     static int per_cu = 0;
@@ -207,13 +200,6 @@ int launch_batched_t(const BatchPlan& p, unsigned* ws, hipStream_t st)
     const unsigned spin_limit = 1u << 21;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, p.args, ws, spin_limit);
     return check_launch("k_edt_batched");
-}
-
-template <int TXY, int TZ>
-int launch_batched_tz(const BatchPlan& p, unsigned* ws, hipStream_t st)
-{
-    return p.nx_max <= 256 ? launch_batched_t<TXY, TZ, 4>(p, ws, st)
-                           : launch_batched_t<TXY, TZ, 8>(p, ws, st);
 }
 
 int launch_batched(const BatchPlan& p, int txy, int tz, unsigned* ws, hipStream_t st)

@@ -9,13 +9,13 @@ namespace {
 
 using namespace tiles;
 
-template <int TW, bool WIDE, int NWMAX, bool FAST>
+template <int TW, bool WIDE>
 __global__ __launch_bounds__(NT) void k_edt_xy(const uint8_t* __restrict__ occ,
                                                uint32_t* __restrict__ xy, int nx, int ny, int nz,
                                                int ntx)
 {
     extern __shared__ uint32_t lds[];
-    edt_xy_tile<TW, WIDE, NWMAX, FAST>(occ, xy, nx, ny, nz, ntx, xcd_remap(blockIdx.x, nz * ntx), lds);
+    edt_xy_tile<TW, WIDE>(occ, xy, nx, ny, nz, ntx, xcd_remap(blockIdx.x, nz * ntx), lds);
 }
 
 template <int TW, bool WIDE, int NTZ>
@@ -42,27 +42,17 @@ int allow_lds(K kernel, bool& done)
     return EDT_OK;
 }
 
-template <int TW, bool WIDE, int NWMAX, bool FAST>
-int launch_xy_t(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, hipStream_t st)
-{
-    static bool done = false;
-    int rc = allow_lds(k_edt_xy<TW, WIDE, NWMAX, FAST>, done);
-    if (rc) return rc;
-    const int ntx = (g->nx + TW - 1) / TW;
-    const size_t lds = xy_lds(TW, g->ny);
-    hipLaunchKernelGGL((k_edt_xy<TW, WIDE, NWMAX, FAST>), dim3(g->nz * ntx), dim3(NT), lds, st, occ,
-                       xy, g->nx, g->ny, g->nz, ntx);
-    return check_launch("k_edt_xy");
-}
-
 template <int TW, bool WIDE>
 int launch_xy_w(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, hipStream_t st)
 {
-    if (g->nx % 64 == 0 && (reinterpret_cast<uintptr_t>(occ) & 15) == 0)
-        return launch_xy_t<TW, WIDE, 4, true>(g, occ, xy, st);
-    if (g->nx <= 256) return launch_xy_t<TW, WIDE, 4, false>(g, occ, xy, st);
-    if (g->nx <= 512) return launch_xy_t<TW, WIDE, 8, false>(g, occ, xy, st);
-    return launch_xy_t<TW, WIDE, 16, false>(g, occ, xy, st);
+    static bool done = false;
+    int rc = allow_lds(k_edt_xy<TW, WIDE>, done);
+    if (rc) return rc;
+    const int ntx = (g->nx + TW - 1) / TW;
+    const size_t lds = xy_lds(TW, g->ny);
+    hipLaunchKernelGGL((k_edt_xy<TW, WIDE>), dim3(g->nz * ntx), dim3(NT), lds, st, occ,
+                       xy, g->nx, g->ny, g->nz, ntx);
+    return check_launch("k_edt_xy");
 }
 
 template <int TW>

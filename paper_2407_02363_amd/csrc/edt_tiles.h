@@ -29,9 +29,10 @@
 // (position | x' << 10 [| y' << 20]), so a key is recomputed from an entry
 // and no side table is needed.
 //
-//   xy tile   work-group = (z slice, TW consecutive columns).  Each wave
-//             reduces whole rows to a 64-bit ballot word for the tile plus
-//             the nearest set bit left and right of it; the (column, band)
+//   xy tile   work-group = (z slice, TW consecutive columns).  The slice
+//             arrives as 16-byte loads turned into a bit string in LDS; one
+//             thread per row cuts out the tile's 64-bit word plus the
+//             nearest set bit left and right of it; the (column, band)
 //             threads derive x' per row from those and feed their stacks.
 //             Output: the 2D site x' | y' << 16 of every voxel, written into
 //             the site buffer (0xFFFFFFFF if the slice is empty).
@@ -402,18 +403,15 @@ __host__ __device__ inline size_t xy_lds(int tw, int nyv)
 }
 
 // One xy tile: slice z, columns [x0, x0 + TW), T = z * ntx + x0 / TW.
-template <int TW, bool WIDE, int NWMAX, bool FAST>
+template <int TW, bool WIDE>
 __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
                                             uint32_t* __restrict__ xy, int nx, int ny, int nz,
                                             int ntx, int T, uint32_t* lds)
 {
     constexpr int NB = NT / TW;
-    constexpr int RB = 32 / NWMAX > 0 ? 32 / NWMAX : 1;   // rows in flight per wave (32 byte loads)
-    constexpr int XCH = 8;                                 // 16-byte loads in flight per thread
-    (void)nz;
+    constexpr int XCH = 8;   // 16-byte loads in flight per thread
     const int L = (ny + NB - 1) / NB;
-    // the 16-byte row path stages rows in the envelope area, which is only
-    // written after step 1
+    // step 1 stages rows in the envelope area, which is only written after it
     const int ent_words = max(NB * L * TW, 2 * XSTAGE_WORDS);
     uint32_t* ent = lds;                                                // [NB*L][TW]
     uint64_t* stage = reinterpret_cast<uint64_t*>(lds);                 // [XSTAGE_WORDS]
@@ -426,102 +424,97 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
     const int z = T / ntx;
     const int x0 = (T - z * ntx) * TW;
     const int w0 = x0 >> 6;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int nwords = (nx + 63) >> 6;
 
     // ---- step 1: per row, the tile's 64-bit occupancy word and the nearest
-    // occupied voxel left and right of the word
-    if constexpr (FAST) {
-        // nx % 64 == 0 and 16-byte aligned rows: blocks of rows arrive as
-        // 16-byte loads, become 16-bit masks in LDS (whole 64-bit words per
-        // row), and one thread per row derives the row record from them
-        const int nw = nx >> 6;
-        const int rblk = min(ny, XSTAGE_WORDS / nw);
+    // occupied voxel left and right of the word.  Blocks of whole rows arrive
+    // as 16-byte loads from 16-byte aligned addresses and become 16-bit masks
+    // in LDS (bit b of the block = byte b - off of the block's first row);
+    // one thread per row then cuts its row's 64-column words out of the bit
+    // string.  Only a chunk that sticks out of the buffer (the first one when
+    // occ is not 16-byte aligned, the last one when the end is not) is read
+    // byte by byte, so no load leaves [occ, occ + n).
+    {
+        constexpr int SBITS = XSTAGE_WORDS * 64;
+        const long long n = (long long)nx * ny * nz;
+        const int mis = (int)((uintptr_t)occ & 15u);
+        const uint4* base16 = reinterpret_cast<const uint4*>(occ - mis);
+        // chunk k covers bytes [16k - mis, 16k - mis + 16) of occ; the whole
+        // ones are k in [kf, ke)
+        const long long kf = mis ? 1 : 0;
+        const long long ke = (n + mis) >> 4;
+        const bool any_whole = ke > kf;
+        const int rblk = min(ny, (SBITS - 32) / nx);
         uint16_t* stage16 = reinterpret_cast<uint16_t*>(stage);
         for (int y0 = 0; y0 < ny; y0 += rblk) {
             const int rows = min(rblk, ny - y0);
-            const int nch = rows * (nx >> 4);
-            const uint4* src = reinterpret_cast<const uint4*>(occ + ((size_t)z * ny + y0) * nx);
+            const long long fs = ((long long)z * ny + y0) * nx;
+            const long long c0 = (fs + mis) >> 4;
+            const int off = (int)((fs + mis) & 15);
+            const int nch = (int)(((fs + (long long)rows * nx - 1 + mis) >> 4) - c0 + 1);
             for (int i0 = 0; i0 < nch; i0 += NT * XCH) {
                 uint4 v[XCH];
+                if (any_whole) {
 #pragma unroll
-                for (int u = 0; u < XCH; ++u) v[u] = src[min(i0 + u * NT + (int)threadIdx.x, nch - 1)];
+                    for (int u = 0; u < XCH; ++u) {
+                        long long k = c0 + min(i0 + u * NT + (int)threadIdx.x, nch - 1);
+                        k = k < kf ? kf : (k >= ke ? ke - 1 : k);
+                        v[u] = base16[k];
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < XCH; ++u) {
                     const int i = i0 + u * NT + (int)threadIdx.x;
-                    if (i < nch)
-                        stage16[i] = (uint16_t)(nonzero_bytes(v[u].x) | (nonzero_bytes(v[u].y) << 4) |
-                                                (nonzero_bytes(v[u].z) << 8) | (nonzero_bytes(v[u].w) << 12));
+                    if (i < nch) {
+                        const long long k = c0 + i;
+                        uint32_t m = 0;
+                        if (k >= kf && k < ke) {
+                            m = nonzero_bytes(v[u].x) | (nonzero_bytes(v[u].y) << 4) |
+                                (nonzero_bytes(v[u].z) << 8) | (nonzero_bytes(v[u].w) << 12);
+                        } else {
+                            for (int j = 0; j < 16; ++j) {
+                                const long long f = 16 * k + j - mis;
+                                if (f >= 0 && f < n && occ[f]) m |= 1u << j;
+                            }
+                        }
+                        stage16[i] = (uint16_t)m;
+                    }
                 }
             }
             __syncthreads();
             for (int r = threadIdx.x; r < rows; r += NT) {
-                const uint64_t* w = stage + r * nw;
+                const int rb = off + r * nx;
+                // columns [64c, 64c + 64) of row r, bits past the row end cleared
+                auto word = [&](int c) -> uint64_t {
+                    const int b = rb + 64 * c;
+                    const int wi = b >> 6, sh = b & 63;
+                    uint64_t w = stage[wi] >> sh;
+                    if (sh) w |= stage[min(wi + 1, XSTAGE_WORDS - 1)] << (64 - sh);
+                    const int valid = nx - 64 * c;
+                    return valid >= 64 ? w : (w & ((1ull << valid) - 1ull));
+                };
                 int left = -1, right = -1;
-                for (int c = w0 - 1; c >= 0; --c)
-                    if (w[c]) {
-                        left = c * 64 + 63 - __clzll(w[c]);
+                for (int c = w0 - 1; c >= 0; --c) {
+                    const uint64_t w = word(c);
+                    if (w) {
+                        left = c * 64 + 63 - __clzll(w);
                         break;
                     }
-                for (int c = w0 + 1; c < nw; ++c)
-                    if (w[c]) {
-                        right = c * 64 + __ffsll((unsigned long long)w[c]) - 1;
+                }
+                for (int c = w0 + 1; c < nwords; ++c) {
+                    const uint64_t w = word(c);
+                    if (w) {
+                        right = c * 64 + __ffsll((unsigned long long)w) - 1;
                         break;
                     }
-                rword[y0 + r] = w[w0];
+                }
+                rword[y0 + r] = word(w0);
                 rleft[y0 + r] = (int16_t)left;
                 rright[y0 + r] = (int16_t)right;
             }
             __syncthreads();
         }
-    } else
-    for (int yb = wave; yb < ny; yb += (NT / 64) * RB) {
-        // unconditional loads from clamped (in-bounds) addresses so that all
-        // RB * NWMAX of them are in flight before the first use; lanes past
-        // the row end are masked afterwards
-        uint8_t b[RB][NWMAX];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int y = min(yb + r * (NT / 64), ny - 1);
-            const uint8_t* row = occ + ((size_t)z * ny + y) * nx;
-#pragma unroll
-            for (int c = 0; c < NWMAX; ++c)
-                b[r][c] = row[min(c * 64 + lane, nx - 1)];
-        }
-#pragma unroll
-        for (int c = 0; c < NWMAX; ++c)
-            if (c * 64 + lane >= nx) {
-#pragma unroll
-                for (int r = 0; r < RB; ++r) b[r][c] = 0;
-            }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int y = yb + r * (NT / 64);
-            if (y >= ny) break;
-            uint64_t mine = 0;
-            int left = -1, right = -1;
-#pragma unroll
-            for (int c = 0; c < NWMAX; ++c) {
-                if (c < nwords) {
-                    const uint64_t mk = __ballot(b[r][c] != 0);
-                    if (c < w0) {
-                        if (mk) left = c * 64 + 63 - __clzll(mk);
-                    } else if (c == w0) {
-                        mine = mk;
-                    } else if (mk && right < 0) {
-                        right = c * 64 + __ffsll((unsigned long long)mk) - 1;
-                    }
-                }
-            }
-            if (lane == 0) {
-                rword[y] = mine;
-                rleft[y] = (int16_t)left;
-                rright[y] = (int16_t)right;
-            }
-        }
     }
-    __syncthreads();
 
     // ---- step 2, band-local: x' per row from the row records, then push
     const int col = threadIdx.x % TW;

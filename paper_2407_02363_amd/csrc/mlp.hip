@@ -7,11 +7,14 @@
 // 4096 x 256 bf16).  Lane l of an MFMA holds A[l % 16][8 (l / 16) + i],
 // B[8 (l / 16) + i][l % 16] and C[4 (l / 16) + i][l % 16].  The epilogue
 // decides what a product becomes:
-//   HID  hidden layer:  bf16(relu(acc + bias))
+//   HID  hidden layer:  bf16(relu(acc + bias)), relu(NaN) = NaN
 //   OUT  output layer:  acc + bias (float32)
 //   DX   upstream gradient: bf16(acc masked where the layer input h > 0)
-//   DW   weight gradient:   acc (float32), the reduction over the batch is
-//        the product's own K loop, so the order is fixed.
+// Weight gradients (a reduction over the batch) have their own kernel,
+// k_gemm_dw: the batch is cut into KS chunks, every (64 x 64 tile, chunk)
+// work-group stages its operands through LDS transposed, writes an FP32
+// partial tile (and the bias partial sums), and k_reduce_dw adds the KS
+// partials in chunk order, so two runs give identical bits.
 #include "common.h"
 #include "sdf_mlp.h"
 
@@ -42,8 +45,18 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 // Workspace layout (bytes) for padded batch P.
 struct WsLayout {
-    size_t x, h1, h2, h3, y, dy, dpa, dpb, part, total;
+    size_t x, h1, h2, h3, y, dy, dpa, dpb, part, dwpart, dbpart, total;
 };
+
+// batch chunks of the weight-gradient reduction: the largest of 16, 8, 4,
+// 2, 1 that cuts the P / 32 MFMA steps evenly
+__host__ __device__ inline int dw_chunks(int P)
+{
+    const int steps = P / 32;
+    int ks = 16;
+    while (steps % ks) ks >>= 1;
+    return ks;
+}
 
 __host__ __device__ inline WsLayout ws_layout(int P)
 {
@@ -63,11 +76,13 @@ __host__ __device__ inline WsLayout ws_layout(int P)
     w.dpa = take((size_t)P * HID * 2);
     w.dpb = take((size_t)P * HID * 2);
     w.part = take(1024 * 4);
+    w.dwpart = take((size_t)dw_chunks(P) * HID * HID * 4);
+    w.dbpart = take((size_t)dw_chunks(P) * HID * 4);
     w.total = o;
     return w;
 }
 
-enum { EPI_HID = 0, EPI_OUT = 1, EPI_DX = 2, EPI_DW = 3 };
+enum { EPI_HID = 0, EPI_OUT = 1, EPI_DX = 2 };
 
 struct GemmArgs {
     const uint16_t* A;
@@ -154,28 +169,130 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
                 const float v = acc[i][j][e];
                 if constexpr (EPI == EPI_HID) {
                     const float z = v + g.bias[n];
-                    g.out16[(size_t)m * g.ldo + n] = f2bf(z > 0.0f ? z : 0.0f);
+                    // ReLU that keeps a NaN (a poisoned row stays visible)
+                    g.out16[(size_t)m * g.ldo + n] = f2bf((z > 0.0f || z != z) ? z : 0.0f);
                 } else if constexpr (EPI == EPI_OUT) {
                     g.out32[(size_t)m * g.ldo + n] = v + g.bias[n];
-                } else if constexpr (EPI == EPI_DX) {
+                } else {
                     const bool on = bf2f(g.mask[(size_t)m * g.ldm + n]) > 0.0f;
                     g.out16[(size_t)m * g.ldo + n] = f2bf(on ? v : 0.0f);
-                } else {
-                    g.out32[(size_t)m * g.ldo + n] = v;
                 }
             }
 }
 
-// x = [sin q1, cos q1, ..., sin q7, cos q7, 0 ...] in bf16; padded rows 0
-__global__ void k_encode(const float* __restrict__ q, int batch, int P, uint16_t* __restrict__ x)
+// Weight-gradient partials.  dW[m][n] = sum_b up[b][m] act[b][n] over the
+// batch rows b of chunk blockIdx.z; M = outputs (rows of up), N = inputs.
+// Both operands arrive as coalesced 16-byte loads of 32 batch rows and are
+// stored transposed in LDS ([m][k] and [n][k], rows padded to 40 elements),
+// so every MFMA operand is one 16-byte LDS read.  The work-groups of the
+// first column of tiles also sum up over their rows (the bias gradient).
+constexpr int DW_LDK = 40;
+
+__global__ __launch_bounds__(256) void k_gemm_dw(const uint16_t* __restrict__ up, int M,
+                                                 const uint16_t* __restrict__ act, int N, int KC,
+                                                 float* __restrict__ dwpart, float* __restrict__ dbpart)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sA[64 * DW_LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[64 * DW_LDK];
+    const int t = threadIdx.x;
+    const int wave = t >> 6;
+    const int lane = t & 63;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int s = blockIdx.z;
+    const int mw = (wave >> 1) * 32, nw = (wave & 1) * 32;
+    const int r = lane & 15;
+    const int kq = (lane >> 4) * 8;
+    // loader: row kr of the 32-row step, 8 columns from c8
+    const int kr = t >> 3, c8 = (t & 7) * 8;
+    const bool bias = blockIdx.x == 0;
+    float bsum = 0.0f;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int kbeg = s * KC;
+    for (int k0 = kbeg; k0 < kbeg + KC; k0 += 32) {
+        uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+        if (m0 + c8 < M) va = *reinterpret_cast<const uint4*>(up + (size_t)(k0 + kr) * M + m0 + c8);
+        if (n0 + c8 < N) vb = *reinterpret_cast<const uint4*>(act + (size_t)(k0 + kr) * N + n0 + c8);
+        const uint16_t* ea = reinterpret_cast<const uint16_t*>(&va);
+        const uint16_t* eb = reinterpret_cast<const uint16_t*>(&vb);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            sA[(c8 + e) * DW_LDK + kr] = ea[e];
+            sB[(c8 + e) * DW_LDK + kr] = eb[e];
+        }
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            a[i] = *reinterpret_cast<const bf16x8*>(sA + (mw + 16 * i + r) * DW_LDK + kq);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            b[j] = *reinterpret_cast<const bf16x8*>(sB + (nw + 16 * j + r) * DW_LDK + kq);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (bias && t < 64) {
+#pragma unroll 8
+            for (int k = 0; k < 32; ++k) bsum += bf2f(sA[t * DW_LDK + k]);
+        }
+        __syncthreads();
+    }
+    float* out = dwpart + (size_t)s * M * N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + mw + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + nw + 16 * j + r;
+                if (m < M && n < N) out[(size_t)m * N + n] = acc[i][j][e];
+            }
+    if (bias && t < 64 && m0 + t < M) dbpart[(size_t)s * M + m0 + t] = bsum;
+}
+
+// grad[m][n] = sum over chunks s = 0 .. KS-1 of the partials, in that order
+__global__ void k_reduce_dw(const float* __restrict__ dwpart, const float* __restrict__ dbpart, int M,
+                            int N, int KS, float* __restrict__ gw, float* __restrict__ gb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int MN = M * N;
+    if (i < MN) {
+        float a = 0.0f;
+        for (int s = 0; s < KS; ++s) a += dwpart[(size_t)s * MN + i];
+        gw[i] = a;
+    } else if (i < MN + M) {
+        const int m = i - MN;
+        float a = 0.0f;
+        for (int s = 0; s < KS; ++s) a += dbpart[(size_t)s * M + m];
+        gb[m] = a;
+    }
+}
+
+// x = [sin q1, cos q1, ..., sin q7, cos q7, 0 ...] in bf16 for state
+// idx[b] (b if idx is NULL); padded rows 0; NaN for an index outside
+// [0, n_rows)
+__global__ void k_encode(const float* __restrict__ q, int n_rows, const int* __restrict__ idx,
+                         int batch, int P, uint16_t* __restrict__ x)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P * INP) return;
     const int b = i / INP, c = i % INP;
     float v = 0.0f;
     if (b < batch && c < 2 * SDF_MLP_JOINTS) {
-        const float a = q[b * SDF_MLP_JOINTS + (c >> 1)];
-        v = (c & 1) ? cosf(a) : sinf(a);
+        const int row = idx ? idx[b] : b;
+        if (row >= 0 && row < n_rows) {
+            const float a = q[(size_t)row * SDF_MLP_JOINTS + (c >> 1)];
+            v = (c & 1) ? cosf(a) : sinf(a);
+        } else {
+            v = __builtin_nanf("");   // an index outside q poisons its row
+        }
     }
     x[i] = f2bf(v);
 }
@@ -188,11 +305,15 @@ __global__ void k_copy_out(const float* __restrict__ y32, int batch, float* __re
     y[i] = y32[(i / SDF_MLP_OUT) * OUTP + i % SDF_MLP_OUT];
 }
 
-// dY = bf16(2 (y - t) / (batch * 12)) on valid entries, 0 elsewhere; block
-// partial sums of (y - t)^2 in a fixed order
+// dY = bf16(2 (y - t) / (batch * 12)) on valid entries, 0 elsewhere, with
+// t = min(target[idx[b]], clip) (clip <= 0: no clipping; NaN for an index
+// outside [0, n_rows)); block partial
+// sums of (y - t)^2 in a fixed order
 __global__ __launch_bounds__(256) void k_loss_dy(const float* __restrict__ y32,
-                                                 const float* __restrict__ t, int batch, int P,
-                                                 uint16_t* __restrict__ dy, float* __restrict__ part)
+                                                 const float* __restrict__ target, int n_rows,
+                                                 const int* __restrict__ idx, float clip, int batch,
+                                                 int P, uint16_t* __restrict__ dy,
+                                                 float* __restrict__ part)
 {
     __shared__ float red[256];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,7 +323,11 @@ __global__ __launch_bounds__(256) void k_loss_dy(const float* __restrict__ y32,
         const int b = i / OUTP, c = i % OUTP;
         float g = 0.0f;
         if (b < batch && c < SDF_MLP_OUT) {
-            const float d = y32[i] - t[b * SDF_MLP_OUT + c];
+            const int row = idx ? idx[b] : b;
+            float t = __builtin_nanf("");   // an index outside target poisons its row
+            if (row >= 0 && row < n_rows) t = target[(size_t)row * SDF_MLP_OUT + c];
+            if (clip > 0.0f && t > clip) t = clip;
+            const float d = y32[i] - t;
             sq = d * d;
             g = d * scale;
         }
@@ -232,17 +357,6 @@ __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ pa
     if (threadIdx.x == 0) *loss = red[0] / (float)(batch * SDF_MLP_OUT);
 }
 
-// db[n] = sum over the P rows of dp[b][n] (bf16), one thread per column, in
-// row order
-__global__ void k_colsum(const uint16_t* __restrict__ dp, int P, int N, int ld, float* __restrict__ db)
-{
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.0f;
-    for (int b = 0; b < P; ++b) s += bf2f(dp[(size_t)b * ld + n]);
-    db[n] = s;
-}
-
 __global__ void k_pack(const float* __restrict__ master, uint16_t* __restrict__ w16, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -266,8 +380,9 @@ __global__ void k_adam(float* __restrict__ w, uint16_t* __restrict__ w16, float*
 }
 
 __global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ y,
-                                                  const float* __restrict__ radii, int batch,
-                                                  float voxel, float thresh, int* __restrict__ need,
+                                                  const float* __restrict__ radii,
+                                                  const float* __restrict__ eps, int batch,
+                                                  float voxel, float margin, int* __restrict__ need,
                                                   int* __restrict__ count)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -275,6 +390,7 @@ __global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ y,
     if (b < batch) {
         for (int i = 0; i < SDF_MLP_OUT; ++i) {
             const float c = y[b * SDF_MLP_OUT + i] * voxel - radii[i];
+            const float thresh = margin + eps[i] * voxel;
             if (!(c >= thresh)) flag = 1;   // NaN predictions also fall back
         }
         need[b] = flag;
@@ -284,6 +400,29 @@ __global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ y,
 }
 
 __global__ void k_zero_int(int* p) { *p = 0; }
+
+__global__ void k_zero_f32(float* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// eps[i] = max(0, max over rows b with target[b][i] < clip of
+// pred[b][i] - target[b][i]) (clip <= 0: every row); a NaN prediction
+// gives +inf.  Non-negative floats order like their bit patterns, so the
+// maximum is an integer atomicMax on the bits and independent of order.
+__global__ __launch_bounds__(256) void k_calibrate(const float* __restrict__ pred,
+                                                   const float* __restrict__ target, int batch,
+                                                   float clip, unsigned* __restrict__ eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= batch * SDF_MLP_OUT) return;
+    const float t = target[i], p = pred[i];
+    if (clip > 0.0f && !(t < clip)) return;
+    float d = p - t;
+    if (p != p) d = __builtin_huge_valf();
+    if (d > 0.0f) atomicMax(eps + i % SDF_MLP_OUT, __float_as_uint(d));
+}
 
 template <bool TA, bool TB, int EPI>
 int gemm(const GemmArgs& a, hipStream_t st)
@@ -328,11 +467,12 @@ int sdf_mlp_pack(const float* master, uint16_t* w16, void* stream)
     return check_launch("k_pack");
 }
 
-int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, int32_t batch,
-                    float* y, void* ws, size_t ws_bytes, void* stream)
+int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, int32_t n_rows,
+                    const int32_t* idx, int32_t batch, float* y, void* ws, size_t ws_bytes,
+                    void* stream)
 {
-    if (!w16 || !master || !q || !ws || batch < 1) {
-        set_error("sdf_mlp_forward: NULL pointer or batch < 1");
+    if (!w16 || !master || !q || !ws || batch < 1 || n_rows < 1 || (!idx && n_rows < batch)) {
+        set_error("sdf_mlp_forward: NULL pointer, batch < 1, or fewer rows than the batch");
         return EDT_ERR_ARG;
     }
     const int P = padded_rows(batch);
@@ -347,7 +487,8 @@ int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, in
                       reinterpret_cast<uint16_t*>(w + L.h3)};
     float* y32 = reinterpret_cast<float*>(w + L.y);
     const hipStream_t st = as_stream(stream);
-    hipLaunchKernelGGL(k_encode, dim3((P * INP + 255) / 256), dim3(256), 0, st, q, (int)batch, P, x);
+    hipLaunchKernelGGL(k_encode, dim3((P * INP + 255) / 256), dim3(256), 0, st, q, (int)n_rows, idx,
+                       (int)batch, P, x);
     int rc = check_launch("k_encode");
     if (rc) return rc;
     const int woff[4] = {SDF_MLP_W1, SDF_MLP_W2, SDF_MLP_W3, SDF_MLP_W4};
@@ -386,11 +527,12 @@ int sdf_mlp_forward(const uint16_t* w16, const float* master, const float* q, in
     return rc;
 }
 
-int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t batch, float* grad,
-                     float* loss, void* ws, size_t ws_bytes, void* stream)
+int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t n_rows, const int32_t* idx,
+                     int32_t batch, float clip_vox, float* grad, float* loss, void* ws, size_t ws_bytes,
+                     void* stream)
 {
-    if (!w16 || !target || !grad || !ws || batch < 1) {
-        set_error("sdf_mlp_backward: NULL pointer or batch < 1");
+    if (!w16 || !target || !grad || !ws || batch < 1 || n_rows < 1 || (!idx && n_rows < batch)) {
+        set_error("sdf_mlp_backward: NULL pointer, batch < 1, or fewer rows than the batch");
         return EDT_ERR_ARG;
     }
     const int P = padded_rows(batch);
@@ -406,13 +548,17 @@ int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t batch, fl
     uint16_t* dy = reinterpret_cast<uint16_t*>(w + L.dy);
     uint16_t* dp[2] = {reinterpret_cast<uint16_t*>(w + L.dpa), reinterpret_cast<uint16_t*>(w + L.dpb)};
     float* part = reinterpret_cast<float*>(w + L.part);
+    float* dwpart = reinterpret_cast<float*>(w + L.dwpart);
+    float* dbpart = reinterpret_cast<float*>(w + L.dbpart);
+    const int KS = dw_chunks(P);
     const hipStream_t st = as_stream(stream);
     const int nblk = (P * OUTP + 255) / 256;
     if (nblk > 1024) {
         set_error("sdf_mlp_backward: batch too large for the loss reduction");
         return EDT_ERR_UNSUPPORTED;
     }
-    hipLaunchKernelGGL(k_loss_dy, dim3(nblk), dim3(256), 0, st, y32, target, (int)batch, P, dy, part);
+    hipLaunchKernelGGL(k_loss_dy, dim3(nblk), dim3(256), 0, st, y32, target, (int)n_rows, idx,
+                       clip_vox, (int)batch, P, dy, part);
     int rc = check_launch("k_loss_dy");
     if (rc) return rc;
     if (loss) {
@@ -425,21 +571,16 @@ int sdf_mlp_backward(const uint16_t* w16, const float* target, int32_t batch, fl
     const int nin[4] = {INP, HID, HID, HID};
     const uint16_t* up = dy;   // upstream gradient of layer l's output, [P][nout]
     for (int l = 3; l >= 0; --l) {
-        // dW_l = up^T act_l : M = nout, N = nin, K = P (rows of the batch)
-        GemmArgs a = args0();
-        a.A = up;
-        a.lda = nout[l];
-        a.B = act[l];
-        a.ldb = nin[l];
-        a.M = nout[l];
-        a.N = nin[l];
-        a.K = P;
-        a.out32 = grad + woff[l];
-        a.ldo = nin[l];
-        if ((rc = gemm<true, false, EPI_DW>(a, st))) return rc;
-        hipLaunchKernelGGL(k_colsum, dim3((nout[l] + 255) / 256), dim3(256), 0, st, up, P, nout[l],
-                           nout[l], grad + boff[l]);
-        if ((rc = check_launch("k_colsum"))) return rc;
+        // dW_l = up^T act_l and db_l = column sums of up: M = nout, N = nin,
+        // reduced over the P rows of the batch in KS chunks
+        const dim3 g((nin[l] + 63) / 64, (nout[l] + 63) / 64, KS);
+        hipLaunchKernelGGL(k_gemm_dw, g, dim3(256), 0, st, up, nout[l], act[l], nin[l], P / KS, dwpart,
+                           dbpart);
+        if ((rc = check_launch("k_gemm_dw"))) return rc;
+        const int nred = nout[l] * nin[l] + nout[l];
+        hipLaunchKernelGGL(k_reduce_dw, dim3((nred + 255) / 256), dim3(256), 0, st, dwpart, dbpart,
+                           nout[l], nin[l], KS, grad + woff[l], grad + boff[l]);
+        if ((rc = check_launch("k_reduce_dw"))) return rc;
         if (l == 0) break;
         // upstream of layer l-1: (up W_l) masked where act_l > 0
         GemmArgs d = args0();
@@ -474,10 +615,10 @@ int sdf_mlp_adam(float* master, uint16_t* w16, float* m, float* v, const float* 
     return check_launch("k_adam");
 }
 
-int sdf_mlp_fallback(const float* y, const float* radii, int32_t batch, float voxel, float margin,
-                     float eps_vox, int32_t* need, int32_t* count, void* stream)
+int sdf_mlp_fallback(const float* y, const float* radii, const float* eps_vox, int32_t batch,
+                     float voxel, float margin, int32_t* need, int32_t* count, void* stream)
 {
-    if (!y || !radii || !need || !count || batch < 1 || !(voxel > 0.0f)) {
+    if (!y || !radii || !eps_vox || !need || !count || batch < 1 || !(voxel > 0.0f)) {
         set_error("sdf_mlp_fallback: bad argument");
         return EDT_ERR_ARG;
     }
@@ -485,9 +626,26 @@ int sdf_mlp_fallback(const float* y, const float* radii, int32_t batch, float vo
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, count);
     int rc = check_launch("k_zero_int");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_fallback, dim3((batch + 255) / 256), dim3(256), 0, st, y, radii, (int)batch,
-                       voxel, margin + eps_vox * voxel, need, count);
+    hipLaunchKernelGGL(k_fallback, dim3((batch + 255) / 256), dim3(256), 0, st, y, radii, eps_vox,
+                       (int)batch, voxel, margin, need, count);
     return check_launch("k_fallback");
+}
+
+int sdf_mlp_calibrate(const float* pred, const float* target, int32_t batch, float clip_vox,
+                      float* eps_vox, void* stream)
+{
+    if (!pred || !target || !eps_vox || batch < 1) {
+        set_error("sdf_mlp_calibrate: NULL pointer or batch < 1");
+        return EDT_ERR_ARG;
+    }
+    const hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, st, eps_vox, (int)SDF_MLP_OUT);
+    int rc = check_launch("k_zero_f32");
+    if (rc) return rc;
+    const int n = batch * SDF_MLP_OUT;
+    hipLaunchKernelGGL(k_calibrate, dim3((n + 255) / 256), dim3(256), 0, st, pred, target, (int)batch,
+                       clip_vox, reinterpret_cast<unsigned*>(eps_vox));
+    return check_launch("k_calibrate");
 }
 
 }  // extern "C"

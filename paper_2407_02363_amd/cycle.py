@@ -16,9 +16,12 @@ from . import edt
 
 
 class ControlCycle:
-    def __init__(self, ci, device="cuda:0", self_mask: int = 0xFF, centres=None):
+    def __init__(self, ci, device="cuda:0", self_mask: int = 0xFF, centres=None,
+                 batched_edt: bool = False):
         """ci: inputs.CycleInputs.  centres: float32 [S, m, 3] per joint
-        state (computed from ci.joint_states by forward kinematics if None)."""
+        state (computed from ci.joint_states by forward kinematics if None).
+        batched_edt: compute both maps' EDTs in one persistent batched launch
+        instead of one edt_compute per map (same results)."""
         from . import inputs
         self.ci = ci
         self.grid = ci.grid
@@ -49,6 +52,11 @@ class ControlCycle:
         self.out_self = edt.new_query_out(m, d)
         self.n_frames = self.frames.shape[0]
         self.n_states = self.poses.shape[0]
+        self.batched_edt = bool(batched_edt)
+        if self.batched_edt:
+            self.maps = edt.batch_maps([ci.grid, ci.grid], [self.occ_env, self.occ_self],
+                                       [self.d2_env, self.d2_self], [self.site_env, self.site_self])
+            self.batch_ws = edt.new_batch_workspace(2, d)
 
     @property
     def voxels_per_cycle(self) -> int:
@@ -65,8 +73,11 @@ class ControlCycle:
                              self.self_mask, stream)
         edt.edt_insert_points(g, self.occ_env, self.frames[f], self.T, exclude=self.occ_self,
                               stream=stream)
-        edt.edt_compute(g, self.occ_env, self.d2_env, self.site_env, stream=stream)
-        edt.edt_compute(g, self.occ_self, self.d2_self, self.site_self, stream=stream)
+        if self.batched_edt:
+            edt.edt_compute_batched(self.maps, self.batch_ws, stream=stream)
+        else:
+            edt.edt_compute(g, self.occ_env, self.d2_env, self.site_env, stream=stream)
+            edt.edt_compute(g, self.occ_self, self.d2_self, self.site_self, stream=stream)
         edt.edt_query_spheres(g, self.d2_env, self.site_env, self.centres[s], self.radii,
                               self.out_env, stream)
         edt.edt_query_spheres(g, self.d2_self, self.site_self, self.centres[s], self.radii,

@@ -21,7 +21,7 @@ LAYOUT = [(W1, B1, N_HIDDEN, IN_PAD), (W2, B2, N_HIDDEN, N_HIDDEN), (W3, B3, N_H
 REAL = [(N_HIDDEN, N_IN), (N_HIDDEN, N_HIDDEN), (N_HIDDEN, N_HIDDEN), (N_OUT, N_HIDDEN)]
 
 EXPORTED = ["sdf_mlp_workspace_bytes", "sdf_mlp_pack", "sdf_mlp_forward", "sdf_mlp_backward",
-            "sdf_mlp_adam", "sdf_mlp_fallback"]
+            "sdf_mlp_adam", "sdf_mlp_fallback", "sdf_mlp_calibrate"]
 _sig_done = False
 
 
@@ -33,10 +33,11 @@ def lib():
         sig = {
             "sdf_mlp_workspace_bytes": ([i32], ctypes.c_size_t),
             "sdf_mlp_pack": ([P, P, P], ctypes.c_int),
-            "sdf_mlp_forward": ([P, P, P, i32, P, P, ctypes.c_size_t, P], ctypes.c_int),
-            "sdf_mlp_backward": ([P, P, i32, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
+            "sdf_mlp_forward": ([P, P, P, i32, P, i32, P, P, ctypes.c_size_t, P], ctypes.c_int),
+            "sdf_mlp_backward": ([P, P, i32, P, i32, f, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
             "sdf_mlp_adam": ([P, P, P, P, P, i32, f, f, f, f, P], ctypes.c_int),
-            "sdf_mlp_fallback": ([P, P, i32, f, f, f, P, P, P], ctypes.c_int),
+            "sdf_mlp_fallback": ([P, P, P, i32, f, f, P, P, P], ctypes.c_int),
+            "sdf_mlp_calibrate": ([P, P, i32, f, P, P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -63,20 +64,37 @@ def sdf_mlp_pack(master, w16, stream=None):
                               _dev(w16, torch.bfloat16, "w16", PARAMS), _stream(stream)), "sdf_mlp_pack")
 
 
-def sdf_mlp_forward(w16, master, q, y, ws, stream=None):
-    """q: float32 [B, 7]; y: float32 [B, 12] or None."""
-    b = q.shape[0]
+def _rows(t, width, name):
+    if t.dim() != 2 or t.shape[1] != width:
+        raise ValueError(f"{name}: expected shape [rows, {width}], got {tuple(t.shape)}")
+    return t.shape[0]
+
+
+def _idx(idx, batch):
+    if idx is None:
+        return None
+    return _dev(idx, torch.int32, "idx", batch)
+
+
+def sdf_mlp_forward(w16, master, q, y, ws, idx=None, stream=None):
+    """q: float32 [R, 7]; idx: int32 [B] row indices into q (None: B = R);
+    y: float32 [B, 12] or None."""
+    rows = _rows(q, JOINTS, "q")
+    b = rows if idx is None else idx.numel()
     _check(lib().sdf_mlp_forward(_dev(w16, torch.bfloat16, "w16", PARAMS),
                                  _dev(master, torch.float32, "master", PARAMS),
-                                 _dev(q, torch.float32, "q", JOINTS * b), b,
+                                 _dev(q, torch.float32, "q", JOINTS * rows), rows, _idx(idx, b), b,
                                  None if y is None else _dev(y, torch.float32, "y", N_OUT * b),
                                  _ptr(ws), ws.numel(), _stream(stream)), "sdf_mlp_forward")
 
 
-def sdf_mlp_backward(w16, target, grad, loss, ws, stream=None):
-    b = target.shape[0]
+def sdf_mlp_backward(w16, target, grad, loss, ws, idx=None, clip_vox=0.0, stream=None):
+    """target: float32 [R, 12]; idx: the same row indices as the forward."""
+    rows = _rows(target, N_OUT, "target")
+    b = rows if idx is None else idx.numel()
     _check(lib().sdf_mlp_backward(_dev(w16, torch.bfloat16, "w16", PARAMS),
-                                  _dev(target, torch.float32, "target", N_OUT * b), b,
+                                  _dev(target, torch.float32, "target", N_OUT * rows), rows,
+                                  _idx(idx, b), b, float(clip_vox),
                                   _dev(grad, torch.float32, "grad", PARAMS),
                                   None if loss is None else _dev(loss, torch.float32, "loss", 1),
                                   _ptr(ws), ws.numel(), _stream(stream)), "sdf_mlp_backward")
@@ -91,13 +109,25 @@ def sdf_mlp_adam(master, w16, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999,
                               float(beta1), float(beta2), float(eps), _stream(stream)), "sdf_mlp_adam")
 
 
-def sdf_mlp_fallback(y, radii, voxel, margin, eps_vox, need, count, stream=None):
+def sdf_mlp_fallback(y, radii, eps_vox, voxel, margin, need, count, stream=None):
+    """eps_vox: float32 [12] device tensor (per-sphere error bound, voxels)."""
     b = y.shape[0]
     _check(lib().sdf_mlp_fallback(_dev(y, torch.float32, "y", N_OUT * b),
-                                  _dev(radii, torch.float32, "radii", N_OUT), b, float(voxel),
-                                  float(margin), float(eps_vox),
-                                  _dev(need, torch.int32, "need", b), _dev(count, torch.int32, "count", 1),
-                                  _stream(stream)), "sdf_mlp_fallback")
+                                  _dev(radii, torch.float32, "radii", N_OUT),
+                                  _dev(eps_vox, torch.float32, "eps_vox", N_OUT), b, float(voxel),
+                                  float(margin), _dev(need, torch.int32, "need", b),
+                                  _dev(count, torch.int32, "count", 1), _stream(stream)),
+           "sdf_mlp_fallback")
+
+
+def sdf_mlp_calibrate(pred, target, clip_vox, eps_vox, stream=None):
+    """eps_vox (float32 [12], device) = per-sphere largest overestimate on
+    the rows whose target lies below clip_vox."""
+    b = pred.shape[0]
+    _check(lib().sdf_mlp_calibrate(_dev(pred, torch.float32, "pred", N_OUT * b),
+                                   _dev(target, torch.float32, "target", N_OUT * b), b,
+                                   float(clip_vox), _dev(eps_vox, torch.float32, "eps_vox", N_OUT),
+                                   _stream(stream)), "sdf_mlp_calibrate")
 
 
 def unpack(master_np: np.ndarray):

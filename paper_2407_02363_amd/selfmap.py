@@ -6,7 +6,9 @@ compute the exact EDT, and read sqrt(d2) at every sphere centre
 (ExtractClosestObstaclePose).  States go in chunks of up to EDT_BATCH_MAX
 maps: one persistent batched EDT launch per chunk, and the whole chunk is
 replayed from a HIP graph whose pose and centre buffers are refilled before
-every replay.  These distances are the surrogate's labels and the judge of
+every replay.  Graphs exist for chunk sizes 1, 2, 4, ... and the full
+chunk, so a partial chunk (the states the surrogate could not clear, for
+instance) costs the next size up rather than a full chunk.  These distances are the surrogate's labels and the judge of
 its error; the same path is the fallback when the surrogate is not trusted.
 Only orchestration lives here.
 """
@@ -37,25 +39,37 @@ class SelfMapLabeler:
         self.out = torch.empty((c, len(setup.sphere_radii), edt.SPHERE_RESULT_WORDS),
                                dtype=torch.int32, device=d)
         self.link_pts = torch.from_numpy(setup.link_pts).to(d)
-        self.maps = edt.batch_maps([g] * c, self.occ, self.d2, self.site)
+        sizes = [1 << k for k in range(7) if (1 << k) < c] + [c]
+        self.maps = {k: edt.batch_maps([g] * k, self.occ[:k], self.d2[:k], self.site[:k])
+                     for k in sizes}
         self.ws = edt.new_batch_workspace(c, d)
-        self.graph = None
+        self.graphs = {}
         if use_graph:
-            self.run_chunk()
+            for k in sizes:
+                self.run_chunk(k)
             torch.cuda.synchronize(d)
-            self.graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(self.graph, capture_error_mode="thread_local"):
-                self.run_chunk()
+            for k in sizes:
+                gr = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gr, capture_error_mode="thread_local"):
+                    self.run_chunk(k)
+                self.graphs[k] = gr
             torch.cuda.synchronize(d)
 
-    def run_chunk(self, stream=None):
+    def size_for(self, k: int) -> int:
+        """Smallest chunk size with a batch plan that holds k states."""
+        return min(s for s in self.maps if s >= k)
+
+    def run_chunk(self, k=None, stream=None):
+        """Clear, insert, transform and query the first k maps (k must be a
+        planned size; None = the full chunk)."""
         g = self.s.grid
-        for i in range(self.chunk):
+        k = self.chunk if k is None else k
+        for i in range(k):
             edt.edt_clear(g, self.occ[i], stream)
             edt.edt_insert_links(g, self.occ[i], self.link_pts, self.s.link_off, self.poses[i],
                                  self.s.mask, stream)
-        edt.edt_compute_batched(self.maps, self.ws, stream=stream)
-        for i in range(self.chunk):
+        edt.edt_compute_batched(self.maps[k], self.ws, stream=stream)
+        for i in range(k):
             edt.edt_query_spheres(g, self.d2[i], self.site[i], self.centres[i], self.radii,
                                   self.out[i], stream)
 
@@ -75,15 +89,16 @@ class SelfMapLabeler:
                                                               device=self.dev)
         for s0 in range(0, n, self.chunk):
             k = min(self.chunk, n - s0)
+            size = self.size_for(k)
             self.poses[:k].copy_(poses_dev[s0:s0 + k])
             self.centres[:k].copy_(centres_dev[s0:s0 + k])
-            if k < self.chunk:   # the unused slots repeat the last state
-                self.poses[k:].copy_(poses_dev[s0 + k - 1].expand(self.chunk - k, -1, -1))
-                self.centres[k:].copy_(centres_dev[s0 + k - 1].expand(self.chunk - k, -1, -1))
-            if self.graph is not None:
-                self.graph.replay()
+            if k < size:   # the unused slots of the plan repeat the last state
+                self.poses[k:size].copy_(poses_dev[s0 + k - 1].expand(size - k, -1, -1))
+                self.centres[k:size].copy_(centres_dev[s0 + k - 1].expand(size - k, -1, -1))
+            if size in self.graphs:
+                self.graphs[size].replay()
             else:
-                self.run_chunk()
+                self.run_chunk(size)
             res[s0:s0 + k].copy_(self.out[:k, :, 6].view(torch.float32))
         return res
 

@@ -37,11 +37,12 @@ def gpu_state(cyc):
 NAMES = ["occ_self", "occ_env", "d2_env", "site_env", "d2_self", "site_self", "q_env", "q_self"]
 
 
-def test_cycle_matches_oracle(oracle_lib):
+@pytest.mark.parametrize("batched_edt", [False, True])
+def test_cycle_matches_oracle(oracle_lib, batched_edt):
     ci = inputs.cycle_inputs(4, n_frames=2, n_states=3)
-    cyc = ControlCycle(ci, "cuda:0")
+    cyc = ControlCycle(ci, "cuda:0", batched_edt=batched_edt)
     for k in range(3):
-        say(f"[cycle] k={k}")
+        say(f"[cycle] k={k} batched_edt={batched_edt}")
         cyc.run(k)
         torch.cuda.synchronize()
         got = gpu_state(cyc)

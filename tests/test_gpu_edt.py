@@ -53,6 +53,21 @@ def test_random_shapes(oracle_lib, shape, density):
     assert_same(occ, oracle_lib, f"random d={density}")
 
 
+@pytest.mark.parametrize("shape,offset", [((5, 64, 128), 1), ((9, 33, 70), 7), ((4, 20, 256), 15),
+                                          ((2, 3, 5), 3), ((1, 1, 1), 9), ((6, 17, 1000), 5)])
+def test_unaligned_occ_and_byte_values(oracle_lib, shape, offset):
+    """occ not 16-byte aligned, bytes around it set to 0xFF (they must not be
+    read as map voxels), and occupied voxels holding arbitrary nonzero byte
+    values (any nonzero byte is occupied)."""
+    g = np.random.Generator(np.random.PCG64(offset))
+    occ = inputs.random_grid(shape, 0.02, offset)
+    occ = (occ * g.integers(1, 256, size=occ.shape)).astype(np.uint8)
+    say(f"[edt parity] unaligned offset={offset} shape={shape}")
+    d2, site = gpu_edt(occ, occ_offset=offset)
+    rd2, rsite = oracle_lib.edt(occ)
+    assert np.array_equal(d2, rd2) and np.array_equal(site, rsite)
+
+
 def test_empty_full_single(oracle_lib):
     assert_same(np.zeros((33, 70, 65), np.uint8), oracle_lib, "empty")
     assert_same(np.ones((9, 70, 65), np.uint8), oracle_lib, "full")

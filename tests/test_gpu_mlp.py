@@ -165,22 +165,71 @@ def test_adam_matches_oracle():
 
 
 def test_fallback_kernel_matches_rule():
+    """The kernel's yes/no per state equals the oracle's rule evaluated in
+    the same float32 order, for per-sphere bounds, including NaN rows."""
     g = inputs.rng(9)
     n = 5000
     y_np = g.uniform(0, 25, (n, 12)).astype(np.float32)
     y_np[17, 3] = np.nan
     radii = g.uniform(0.02, 0.05, 12).astype(np.float32)
-    voxel, margin, eps = 0.01, 0.05, 1.7
+    eps = g.uniform(0.0, 3.0, 12).astype(np.float32)
+    voxel, margin = 0.01, 0.05
     s = Surrogate(dev(), seed=0, batch=64)
     need, count = s.fallback(torch.from_numpy(y_np).to(dev()), torch.from_numpy(radii).to(dev()),
-                             voxel, margin, eps)
+                             voxel, margin, torch.from_numpy(eps).to(dev()))
     torch.cuda.synchronize()
     ref = M.needs_exact(y_np, radii, voxel, margin, eps)
-    clear = y_np.astype(np.float64) * voxel - radii[None, :]
-    near = (np.abs(clear - (margin + eps * voxel)) < 1e-6).any(1)   # float32 ties
     got = need.cpu().numpy().astype(bool)
-    assert np.array_equal(got[~near], ref[~near]) and got[17]
-    assert int(count.item()) == int(got.sum())
+    assert np.array_equal(got, ref) and got[17]
+    assert 0 < got.sum() < n and int(count.item()) == int(got.sum())
+
+
+def test_calibrate_matches_oracle():
+    g = inputs.rng(10)
+    n = 3000
+    t_np = g.uniform(0, 40, (n, 12)).astype(np.float32)
+    p_np = (t_np + g.normal(0, 1.5, (n, 12))).astype(np.float32)
+    p_np[5, 7] = np.nan
+    t = torch.from_numpy(t_np).to(dev())
+    p = torch.from_numpy(p_np).to(dev())
+    eps = torch.full((12,), -1.0, dtype=torch.float32, device=dev())
+    for clip in (24.0, 0.0):
+        mlp.sdf_mlp_calibrate(p, t, clip, eps)
+        torch.cuda.synchronize()
+        ref = M.calibrate(p_np, t_np, clip)
+        assert np.array_equal(eps.cpu().numpy(), ref), clip
+        assert np.isinf(ref[7]) and (ref[np.arange(12) != 7] > 0).all()
+
+
+def test_gather_and_clip_match_plain():
+    """A minibatch named by row indices, with clipped targets, gives the same
+    bits as the gathered rows and pre-clipped targets passed directly."""
+    rows, batch, clip = 1000, 448, 12.0
+    s = perturbed_surrogate(14)
+    q_np = inputs.random_joint_states(rows, 15).astype(np.float32)
+    t_np = inputs.rng(16).uniform(0, 20, (rows, 12)).astype(np.float32)
+    idx_np = inputs.rng(17).permutation(rows)[:batch].astype(np.int32)
+    q, t = torch.from_numpy(q_np).to(dev()), torch.from_numpy(t_np).to(dev())
+    idx = torch.from_numpy(idx_np).to(dev())
+    y1 = torch.empty((batch, 12), dtype=torch.float32, device=dev())
+    mlp.sdf_mlp_forward(s.w16, s.master, q, y1, s.ws, idx=idx)
+    mlp.sdf_mlp_backward(s.w16, t, s.grad, s.loss, s.ws, idx=idx, clip_vox=clip)
+    torch.cuda.synchronize()
+    g1, l1 = s.grad.clone(), s.loss.clone()
+    qg = torch.from_numpy(q_np[idx_np]).to(dev())
+    tg = torch.from_numpy(np.minimum(t_np[idx_np], np.float32(clip))).to(dev())
+    y2 = torch.empty((batch, 12), dtype=torch.float32, device=dev())
+    mlp.sdf_mlp_forward(s.w16, s.master, qg, y2, s.ws)
+    mlp.sdf_mlp_backward(s.w16, tg, s.grad, s.loss, s.ws)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2) and torch.equal(g1, s.grad) and torch.equal(l1, s.loss)
+    # an index outside q poisons only its own row
+    bad = idx.clone()
+    bad[3] = rows
+    mlp.sdf_mlp_forward(s.w16, s.master, q, y1, s.ws, idx=bad)
+    torch.cuda.synchronize()
+    yb = y1.cpu().numpy()
+    assert np.isnan(yb[3]).all() and np.array_equal(np.delete(yb, 3, 0), np.delete(y2.cpu().numpy(), 3, 0))
 
 
 def test_labeler_matches_oracle(oracle_lib):
@@ -218,32 +267,36 @@ def test_training_is_deterministic_and_learns():
 
 
 def test_surrogate_gain_with_zero_misses():
-    """Trained on exact-EDT labels, the surrogate plus fallback rule never
-    calls a state safe that the exact transform puts inside the margin, and
-    skips the exact transform for a real share of the look-ahead states."""
+    """Trained on exact-EDT labels, with its error bound calibrated per sphere
+    on held-out states, the surrogate plus fallback rule never calls a state
+    safe that the exact transform puts inside the margin, and skips the exact
+    transform for a real share of the look-ahead states."""
     from paper_2407_02363_amd.selfmap import SelfMapLabeler
     st = inputs.self_map_setup()
     lab = SelfMapLabeler(st, chunk=48, device=dev())
-    q_tr = inputs.random_joint_states(40960, 21)
-    q_va = inputs.random_joint_states(8192, 22)
-    q_te = inputs.random_joint_states(8192, 23)
-    say("[mlp] labelling 57k states")
+    q_tr = inputs.random_joint_states(131072, 21)
+    q_va = inputs.random_joint_states(16384, 22)
+    q_te = inputs.random_joint_states(16384, 23)
+    say("[mlp] labelling 164k states")
     y_tr, y_va, y_te = lab.labels(q_tr), lab.labels(q_va), lab.labels(q_te)
-    s = Surrogate(dev(), seed=3, batch=4096)
+    s = Surrogate(dev(), seed=3, batch=4096, clip_vox=24.0)
+    margin = 0.05
+    # the clip must sit above every distance that can decide a state
+    assert (margin + st.sphere_radii.max()) / st.grid.voxel + 8.0 < s.clip_vox
     t = lambda a: torch.from_numpy(a.astype(np.float32)).to(dev())
-    hist = s.train(t(q_tr), y_tr, epochs=40, lr=2e-3, seed=2)
-    p_va = s.predict(t(q_va))
-    eps = float((p_va - y_va).abs().max().item())
+    hist = s.train(t(q_tr), y_tr, epochs=40, lr=2e-3, seed=2, lr_final=2e-5)
+    eps = s.calibrate(t(q_va), y_va).cpu().numpy()
+    assert (eps < 8.0).all(), eps
     p_te = s.predict(t(q_te))
     radii = torch.from_numpy(st.sphere_radii).to(dev())
-    need, count = s.fallback(p_te, radii, st.grid.voxel, 0.05, eps)
+    need, count = s.fallback(p_te, radii, st.grid.voxel, margin)
     torch.cuda.synchronize()
     need = need.cpu().numpy().astype(bool)
     exact_clear = y_te.cpu().numpy().astype(np.float64) * st.grid.voxel - st.sphere_radii[None, :]
-    truly_near = (exact_clear < 0.05).any(1)
+    truly_near = (exact_clear < margin).any(1)
     misses = int((truly_near & ~need).sum())
     skipped = 1.0 - need.mean()
-    say(f"[mlp] loss {hist[0]:.2f}->{hist[-1]:.3f}, eps_max {eps:.2f} vox, "
+    say(f"[mlp] loss {hist[0]:.2f}->{hist[-1]:.3f}, eps {np.round(eps, 2)} vox, "
         f"fallback {need.mean():.3f}, truly near {truly_near.mean():.3f}, misses {misses}")
     assert misses == 0
     assert skipped > 0.15

@@ -125,3 +125,46 @@ def test_fallback_rule():
     assert need.tolist() == [False, True]
     assert M.needs_exact(pred, r, 0.01, 0.05, 2.0).tolist() == [False, True]
     assert M.needs_exact(pred, r, 0.01, 0.05, 3.5).tolist() == [True, True]
+
+
+def test_fallback_rule_per_sphere_and_nan():
+    pred = np.full((3, 12), 10.0)
+    pred[1, 5] = 7.0          # clearance 0.07 - 0.02 = 0.05 m
+    pred[2, 0] = np.nan
+    r = np.full(12, 0.02)
+    eps = np.zeros(12)
+    # sphere 5 has clearance 0.05 m: inside margin + its bound only once
+    # its bound is positive; the other spheres' bounds do not matter for it
+    assert M.needs_exact(pred, r, 0.01, 0.04, eps).tolist() == [False, False, True]
+    eps[5] = 1.5              # 0.05 < 0.04 + 0.015
+    assert M.needs_exact(pred, r, 0.01, 0.04, eps).tolist() == [False, True, True]
+    eps[:] = 0.0
+    eps[3] = 5.0              # sphere 3: 0.08 < 0.04 + 0.05 in every state
+    assert M.needs_exact(pred, r, 0.01, 0.04, eps).tolist() == [True, True, True]
+
+
+def test_calibrate_by_hand():
+    tgt = np.zeros((3, 12))
+    pred = np.zeros((3, 12))
+    tgt[:, 0], pred[:, 0] = [1.0, 2.0, 30.0], [1.5, 1.0, 45.0]   # row 2 above the clip: ignored
+    tgt[:, 1], pred[:, 1] = [5.0, 5.0, 5.0], [9.0, 4.0, 6.0]     # largest overestimate 4
+    tgt[:, 2], pred[:, 2] = [3.0, 3.0, 3.0], [1.0, 2.0, 3.0]     # only underestimates: 0
+    pred[0, 3] = np.nan                                           # a NaN prediction: unbounded
+    e = M.calibrate(pred, tgt, 24.0)
+    assert e.dtype == np.float32
+    assert e[0] == np.float32(0.5) and e[1] == 4.0 and e[2] == 0.0 and np.isinf(e[3])
+    assert (e[4:] == 0.0).all()
+    # without a clip the far row counts too
+    assert M.calibrate(pred, tgt, 0.0)[0] == 15.0
+
+
+def test_loss_with_clip_by_hand():
+    y = np.zeros((1, 12))
+    t = np.zeros((1, 12))
+    y[0, 4], t[0, 4] = 30.0, 40.0
+    loss, dy = M.loss_and_dy(y, t, rounding=False, clip=24.0)
+    assert loss == 36.0 / 12 and dy[0, 4] == 1.0 and (np.delete(dy, 4) == 0).all()
+    loss_nc, _ = M.loss_and_dy(y, t, rounding=False)
+    assert loss_nc == 100.0 / 12
+    # a clip above every target changes nothing
+    assert M.loss_and_dy(y, t, rounding=False, clip=50.0)[0] == loss_nc
