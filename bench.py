@@ -22,8 +22,10 @@ Printed as one JSON line:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -39,6 +41,41 @@ METRIC = "EDT Mvoxels/s + % HBM roofline; p50/p99 insert→EDT→query cycle lat
 XY_BYTES_PER_VOXEL = 1 + 4      # occupancy byte in, packed 2D site out
 Z_BYTES_PER_VOXEL = 4 + 8       # packed 2D site in, d2 + site out
 EDT_BYTES_PER_VOXEL = 9         # compulsory: occupancy in, d2 + site out
+
+
+# HBM traffic of the EDT kernels from hardware counters: a committed summary
+# of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this benchmark,
+# scaled by the same counters on a device copy of known size.  It is used
+# only while the kernel sources hash to what they were when it was taken.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "edt_cycle256_pmc_traffic.md")
+EDT_KERNEL_SOURCES = ("paper_2407_02363_amd/csrc/common.h", "paper_2407_02363_amd/csrc/edt_tiles.h",
+                      "paper_2407_02363_amd/csrc/edt_core.hip")
+
+
+def edt_source_hash():
+    h = hashlib.sha256()
+    for f in EDT_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of kernel on the control-cycle map, or None when
+    no counter summary exists for the current kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_sha256") != edt_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -444,7 +481,7 @@ def main():
     kd = kernels[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBs"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["achieved_GBs"] / HBM_PEAK_GBS,
-                "traffic": None,
+                "traffic": measured_traffic(dom),
                 "algorithmic_bytes_per_launch": kd["bytes_per_voxel"] * nvox}
     edt_alg = EDT_BYTES_PER_VOXEL * nvox / (t_all * 1e-3) / 1e9
     edt_only = {"avg_us": 1e3 * t_all, "mvox_s": nvox / (t_all * 1e-3) / 1e6,

@@ -51,8 +51,12 @@ __global__ void k_batch_reset(unsigned* ws, int n)
     if (i < n) ws[i] = 0u;
 }
 
+// At most 128 VGPRs, so that 4 waves fit per SIMD: the LDS of the larger
+// tiles allows 4 work-groups per CU, and the register allocator would
+// otherwise take more for the fused xy + z body than either part needs.
 template <int TXY, int TZ>
-__global__ __launch_bounds__(NT) void k_edt_batched(BatchArgs a, unsigned* ws, unsigned spin_limit)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_edt_batched(BatchArgs a, unsigned* ws, unsigned spin_limit)
 {
     extern __shared__ uint32_t lds[];
     __shared__ int s_item;
