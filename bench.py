@@ -86,24 +86,37 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def time_stage(edt, torch, grid, occ, d2, site, stage, reps):
-    """Average duration (ms) of one EDT stage over reps launches, each
-    bracketed by HIP events recorded on the stream the kernel runs on.  The
-    z stage rewrites its input in place, so an untimed xy stage refreshes
-    that input before every timed z launch."""
+def time_block(torch, fn, reps):
+    """Average duration (ms) of fn() over reps back-to-back calls, from one
+    pair of HIP events on the stream the kernels run on (3 untimed calls
+    first)."""
     st = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
-    for i in range(reps + 3):
-        if stage == edt.STAGE_Z:
-            edt.edt_compute_stage(grid, occ, d2, site, edt.STAGE_XY)
-        if i >= 3:
-            ev[i - 3][0].record(st)
-        edt.edt_compute_stage(grid, occ, d2, site, stage)
-        if i >= 3:
-            ev[i - 3][1].record(st)
-    st.synchronize()
-    return sum(a.elapsed_time(b) for a, b in ev) / reps
+    for _ in range(3):
+        fn()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        fn()
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def time_edt_kernels(edt, torch, grid, occ, d2, site, reps):
+    """Average kernel durations (ms) of the xy pass, the z pass and the whole
+    transform.  The z pass rewrites its input in place, so it runs after an
+    xy pass every time: z = (xy then z) - xy, both timed back to back."""
+    run = lambda stage: (lambda: edt.edt_compute_stage(grid, occ, d2, site, stage))
+    t_xy = time_block(torch, run(edt.STAGE_XY), reps)
+
+    def pair():
+        edt.edt_compute_stage(grid, occ, d2, site, edt.STAGE_XY)
+        edt.edt_compute_stage(grid, occ, d2, site, edt.STAGE_Z)
+
+    t_pair = time_block(torch, pair, reps)
+    t_all = time_block(torch, run(edt.STAGE_ALL), reps)
+    return t_xy, t_pair - t_xy, t_all
 
 
 def cpu_baseline(ci, budget_s: float):
@@ -138,9 +151,10 @@ def cpu_baseline(ci, budget_s: float):
 
 
 def batched_workload(args, torch, edt, inputs, host_latency=True):
-    """Many maps of uneven size: per-map launches vs one persistent launch,
-    eager and graph-replayed; every variant runs the whole cycle (clear,
-    insert, EDT, sphere queries at every look-ahead state)."""
+    """Many maps of uneven size: per-map launches vs one persistent launch vs
+    one launch per pass over all maps, eager and graph-replayed; every
+    variant runs the whole cycle (clear, insert, EDT, sphere queries at every
+    look-ahead state)."""
     from paper_2407_02363_amd.batch_cycle import BatchCycle
     log(f"[bench] batched workload: generating {args.batch_maps} maps")
     bi = inputs.batch_inputs(seed=0, n_maps=args.batch_maps, n_states=16)
@@ -180,10 +194,12 @@ def batched_workload(args, torch, edt, inputs, host_latency=True):
            "maps": len(bi.grids), "voxels_per_cycle": bc.voxels, "queries_per_cycle": bc.queries,
            "points_per_cycle": int(sum(c.shape[0] for c in bi.clouds)),
            "batch_tiles": list(tiles), "autotuned_edt_us": tuned_us}
-    graphs = {"plain": bc.capture(bc.run_plain), "batched": bc.capture(bc.run_batched)}
-    for name, fn in [("plain", bc.run_plain), ("batched", bc.run_batched),
+    graphs = {"plain": bc.capture(bc.run_plain), "batched": bc.capture(bc.run_batched),
+              "many": bc.capture(bc.run_many)}
+    for name, fn in [("plain", bc.run_plain), ("batched", bc.run_batched), ("many", bc.run_many),
                      ("plain_graph", graphs["plain"].replay),
-                     ("batched_graph", graphs["batched"].replay)]:
+                     ("batched_graph", graphs["batched"].replay),
+                     ("many_graph", graphs["many"].replay)]:
         log(f"[bench] batched workload: {name}")
         ms = timed(fn, max(20, n // 10))
         r = {"ms_per_cycle": ms, "mvox_s": bc.voxels / (ms * 1e-3) / 1e6}
@@ -196,6 +212,7 @@ def batched_workload(args, torch, edt, inputs, host_latency=True):
         lambda: [edt.edt_compute(g, o, d, s) for g, o, d, s in
                  zip(bc.grids, bc.occ, bc.d2, bc.site)], 50)
     res["edt_only_batched_ms"] = timed(lambda: edt.edt_compute_batched(bc.maps, bc.ws), 50)
+    res["edt_only_many_ms"] = timed(lambda: edt.edt_compute_many(bc.maps), 50)
     if edt.edt_batch_status(bc.ws):
         raise SystemExit("batched EDT reported a timed-out wait")
     return res
@@ -370,7 +387,7 @@ def main():
         del src, dst
     log("[bench] generating inputs")
     ci = inputs.cycle_inputs(0, n_frames=args.frames, n_states=args.states)
-    cyc = ControlCycle(ci, dev)
+    cyc = ControlCycle(ci, dev, edt_mode="many")
     g = ci.grid
     st = torch.cuda.current_stream()
 
@@ -441,35 +458,40 @@ def main():
         latency["graph"] = {"p50_ms": pct(lat_graph, 50), "p99_ms": pct(lat_graph, 99),
                             "cycles": len(lat_graph)}
 
-    # ---- the same cycle with both EDTs in one persistent batched launch
-    log("[bench] cycle with the two-map batched EDT")
-    cyc_b = ControlCycle(ci, dev, batched_edt=True)
-    for k in range(args.warmup):
-        cyc_b.run(k)
-    cyc_b.run(1)
-    cyc.run(1)
-    torch.cuda.synchronize()
-    if not (torch.equal(cyc_b.d2_env, cyc.d2_env) and torch.equal(cyc_b.site_self, cyc.site_self)
-            and torch.equal(cyc_b.out_env, cyc.out_env)):
-        raise SystemExit("batched-EDT cycle differs from the per-map cycle")
-    el_b = run_steps(cyc_b.run, args.steps)
-    cycle_batched = {"eager_ms_per_cycle": 1e3 * el_b / args.steps}
-    if args.graphs > 0:
-        graphs_b = cyc_b.capture_graphs(args.graphs)
-        el_bg = run_steps(lambda k: graphs_b[k % len(graphs_b)].replay(), args.steps)
-        cycle_batched.update({"graph_ms_per_cycle": 1e3 * el_bg / args.steps,
-                              "graph_mvox_s": cyc_b.voxels_per_cycle * args.steps / el_bg / 1e6})
-        del graphs_b
-    del cyc_b
+    # ---- the same cycle with the EDTs run other ways (identical results)
+    variants = {}
+    for name, kw in (("per_map", {"edt_mode": "per_map"}),
+                     ("per_map_two_streams", {"edt_mode": "per_map", "two_streams": True}),
+                     ("batched_persistent", {"edt_mode": "batched"})):
+        log(f"[bench] cycle variant {name}")
+        cv = ControlCycle(ci, dev, **kw)
+        for k in range(args.warmup):
+            cv.run(k)
+        cv.run(1)
+        cyc.run(1)
+        torch.cuda.synchronize()
+        if not all(torch.equal(a, b) for a, b in
+                   ((cv.d2_env, cyc.d2_env), (cv.site_env, cyc.site_env), (cv.d2_self, cyc.d2_self),
+                    (cv.site_self, cyc.site_self), (cv.out_env, cyc.out_env),
+                    (cv.out_self, cyc.out_self))):
+            raise SystemExit(f"cycle variant {name} differs from the default cycle")
+        el_v = run_steps(cv.run, args.steps)
+        r = {"eager_ms_per_cycle": 1e3 * el_v / args.steps}
+        if args.graphs > 0:
+            gv = cv.capture_graphs(args.graphs)
+            el_vg = run_steps(lambda k: gv[k % len(gv)].replay(), args.steps)
+            r.update({"graph_ms_per_cycle": 1e3 * el_vg / args.steps,
+                      "graph_mvox_s": cv.voxels_per_cycle * args.steps / el_vg / 1e6})
+            del gv
+        variants[name] = r
+        del cv
 
     # ---- per-kernel timing and roofline on the environment map
     log("[bench] per-kernel timing")
     cyc.run(0)
     torch.cuda.synchronize()
     occ, d2, site = cyc.occ_env, cyc.d2_env, cyc.site_env
-    t_xy = time_stage(edt, torch, g, occ, d2, site, edt.STAGE_XY, args.kernel_reps)
-    t_z = time_stage(edt, torch, g, occ, d2, site, edt.STAGE_Z, args.kernel_reps)
-    t_all = time_stage(edt, torch, g, occ, d2, site, edt.STAGE_ALL, args.kernel_reps)
+    t_xy, t_z, t_all = time_edt_kernels(edt, torch, g, occ, d2, site, args.kernel_reps)
     nvox = g.n
     kernels = {
         "k_edt_xy": {"avg_us": 1e3 * t_xy, "bytes_per_voxel": XY_BYTES_PER_VOXEL},
@@ -507,7 +529,7 @@ def main():
                       "points_per_frame": int(ci.frames[0].shape[0]),
                       "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
            "timing": mode, "eager": eager, "latency": latency,
-           "cycle_batched_edt": cycle_batched, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
+           "cycle_variants": variants, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
            "batched": batched, "surrogate": surrogate,
            "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",
                              "workload": "live camera scene, 256x256x128 at 1 cm"}}

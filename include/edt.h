@@ -207,11 +207,30 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
 #define EDT_BATCH_MAX 48
 
 typedef struct edt_batch_map_t {
-    edt_grid_t grid;      /* every axis <= 512 voxels */
+    edt_grid_t grid;      /* edt_compute_batched: every axis <= 512 voxels */
     const uint8_t* occ;   /* device, as for edt_compute */
     int32_t* d2;          /* device out */
     int32_t* site;        /* device out */
 } edt_batch_map_t;
+
+/*
+ * edt_compute_many -- exact EDT (as edt_compute, Sec. III-C / Alg. 1) of
+ * several maps in two launches: one xy launch over the tiles of every map,
+ * then one z launch.  Maps may differ in shape (each axis up to 1024); a
+ * map's work-groups start as soon as the previous map's free the GPU, so
+ * each pass's slowest work-groups overlap other maps' work instead of
+ * idling the GPU.  No workspace and no synchronisation; graph-capturable.
+ *   maps    HOST array of n_maps (1..EDT_BATCH_MAX) descriptors, read during
+ *           the call; buffers of different maps must not overlap.
+ *   tuning  NULL = the tiles edt_compute would use for a grid with every
+ *           map's largest extents; else as for edt_compute_tuned, valid for
+ *           those extents.
+ * Results are identical to one edt_compute per map.  Errors: argument and
+ * shape errors as for edt_compute, EDT_ERR_UNSUPPORTED for tiles that do
+ * not fit the largest map.
+ */
+int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuning_t* tuning,
+                     void* stream);
 
 /* Workspace bytes for a batch of n_maps (queue head, error flag, one
  * counter per map). */

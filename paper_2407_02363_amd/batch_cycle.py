@@ -6,6 +6,7 @@ query launch per map for all states).  Two ways to run the EDT of the batch:
 
   run_plain    one edt_compute per map (two kernels per map)
   run_batched  one edt_compute_batched for all maps (one persistent launch)
+  run_many     one edt_compute_many for all maps (one launch per pass)
 
 Either can be captured into a HIP graph.  Only orchestration lives here.
 """
@@ -67,8 +68,13 @@ class BatchCycle:
         edt.edt_compute_batched(self.maps, self.ws, stream=stream)
         self._query(stream)
 
+    def run_many(self, stream=None):
+        self._insert(stream)
+        edt.edt_compute_many(self.maps, stream=stream)
+        self._query(stream)
+
     def capture(self, fn):
-        """HIP graph of one cycle (fn = run_plain or run_batched)."""
+        """HIP graph of one cycle (fn = run_plain, run_batched or run_many)."""
         fn()
         torch.cuda.synchronize(self.dev)
         g = torch.cuda.CUDAGraph()

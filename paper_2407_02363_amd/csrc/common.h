@@ -51,6 +51,30 @@ bool needs_wide(const edt_grid_t* g);
 int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st);
 int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st);
 
+// One launch per pass over the tiles of several maps: tile T of the launch
+// belongs to the map whose [begin, begin + tiles) holds it.  Passed by value
+// as the kernel argument (about 2.3 KiB).
+struct EdtMap {
+    const uint8_t* occ;
+    int32_t* d2;
+    int32_t* site;   // the packed 2D sites between the passes
+    int nx, ny, nz;
+    int ntx;         // column tiles per row of this pass
+    int begin;       // first tile of this map in the launch
+};
+struct EdtMapSet {
+    int n;
+    int total;       // tiles of all maps
+    int ny_max, nz_max;
+    bool wide;
+    EdtMap m[EDT_BATCH_MAX];
+};
+// Validates the maps and the tiles and fills the two passes' sets.
+int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMapSet& xy,
+                  EdtMapSet& z);
+int launch_edt_xy_set(const EdtMapSet& s, int tw, hipStream_t st);
+int launch_edt_z_set(const EdtMapSet& s, int tw, int nt, hipStream_t st);
+
 // Work-group index remap so that consecutive logical tiles land on the same
 // XCD (the dispatcher deals work-groups to the 8 XCDs round-robin).  A
 // bijection of [0, G).

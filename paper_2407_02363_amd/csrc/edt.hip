@@ -377,6 +377,37 @@ int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t
     return edt_compute_stage(grid, occ, d2, site, EDT_STAGE_ALL, nullptr, stream);
 }
 
+int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuning_t* tuning,
+                     void* stream)
+{
+    if (!maps || n_maps < 1 || n_maps > EDT_BATCH_MAX) {
+        set_error("edt_compute_many: need 1..%d maps, got %d", EDT_BATCH_MAX, n_maps);
+        return EDT_ERR_ARG;
+    }
+    EdtTuning t;
+    if (tuning) {
+        t.xy_tw = tuning->xy_tile;
+        t.z_tw = tuning->z_tile;
+        t.z_nt = tuning->z_group ? tuning->z_group : 256;
+    } else {
+        edt_grid_t big = maps[0].grid;
+        for (int i = 1; i < n_maps; ++i) {
+            big.nx = std::max(big.nx, maps[i].grid.nx);
+            big.ny = std::max(big.ny, maps[i].grid.ny);
+            big.nz = std::max(big.nz, maps[i].grid.nz);
+        }
+        if (check_grid(&big)) return check_grid(&big);
+        t = current_tuning(&big);
+    }
+    static thread_local EdtMapSet sxy, sz;   // ~2.3 KiB each: kept off the stack
+    int rc = make_map_sets(maps, n_maps, t, sxy, sz);
+    if (rc) return rc;
+    const hipStream_t st = as_stream(stream);
+    rc = launch_edt_xy_set(sxy, t.xy_tw, st);
+    if (!rc) rc = launch_edt_z_set(sz, t.z_tw, t.z_nt, st);
+    return rc;
+}
+
 int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* site,
                       const float* centres, const float* radii, int32_t m,
                       edt_sphere_result_t* out, void* stream)

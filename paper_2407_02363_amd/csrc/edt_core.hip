@@ -1,6 +1,8 @@
 // The exact squared EDT on gfx950 for one map: the xy-tile kernel (steps 1-3
 // of Sec. III-C in every slice) and the z-tile kernel (step 4), their
 // launchers and the tile heuristics.  The tile code is in edt_tiles.h.
+#include <algorithm>
+
 #include "edt_tiles.h"
 
 namespace edtmi {
@@ -9,21 +11,31 @@ namespace {
 
 using namespace tiles;
 
+// Map of launch tile T (the maps' tile ranges are consecutive).
+__device__ __forceinline__ int map_of(const EdtMapSet& s, int T)
+{
+    int m = 0;
+    while (m + 1 < s.n && s.m[m + 1].begin <= T) ++m;
+    return __builtin_amdgcn_readfirstlane(m);
+}
+
 template <int TW, bool WIDE>
-__global__ __launch_bounds__(NT) void k_edt_xy(const uint8_t* __restrict__ occ,
-                                               uint32_t* __restrict__ xy, int nx, int ny, int nz,
-                                               int ntx)
+__global__ __launch_bounds__(NT) void k_edt_xy(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
-    edt_xy_tile<TW, WIDE>(occ, xy, nx, ny, nz, ntx, xcd_remap(blockIdx.x, nz * ntx), lds);
+    const int T = xcd_remap(blockIdx.x, s.total);
+    const EdtMap& d = s.m[map_of(s, T)];
+    edt_xy_tile<TW, WIDE>(d.occ, reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny, d.nz, d.ntx,
+                          T - d.begin, lds);
 }
 
 template <int TW, bool WIDE, int NTZ>
-__global__ __launch_bounds__(NTZ) void k_edt_z(int32_t* d2, int32_t* site, int nx, int ny, int nz,
-                                               int ntx)
+__global__ __launch_bounds__(NTZ) void k_edt_z(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
-    edt_z_tile<TW, WIDE, NTZ>(d2, site, nx, ny, nz, ntx, xcd_remap(blockIdx.x, ny * ntx), lds);
+    const int T = xcd_remap(blockIdx.x, s.total);
+    const EdtMap& d = s.m[map_of(s, T)];
+    edt_z_tile<TW, WIDE, NTZ>(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, lds);
 }
 
 // Allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per
@@ -43,41 +55,62 @@ int allow_lds(K kernel, bool& done)
 }
 
 template <int TW, bool WIDE>
-int launch_xy_w(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, hipStream_t st)
+int launch_xy_w(const EdtMapSet& s, hipStream_t st)
 {
     static bool done = false;
     int rc = allow_lds(k_edt_xy<TW, WIDE>, done);
     if (rc) return rc;
-    const int ntx = (g->nx + TW - 1) / TW;
-    const size_t lds = xy_lds(TW, g->ny);
-    hipLaunchKernelGGL((k_edt_xy<TW, WIDE>), dim3(g->nz * ntx), dim3(NT), lds, st, occ,
-                       xy, g->nx, g->ny, g->nz, ntx);
+    hipLaunchKernelGGL((k_edt_xy<TW, WIDE>), dim3(s.total), dim3(NT), xy_lds(TW, s.ny_max), st, s);
     return check_launch("k_edt_xy");
 }
 
 template <int TW>
-int launch_xy_tw(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, bool wide, hipStream_t st)
+int launch_xy_tw(const EdtMapSet& s, hipStream_t st)
 {
-    return wide ? launch_xy_w<TW, true>(g, occ, xy, st) : launch_xy_w<TW, false>(g, occ, xy, st);
+    return s.wide ? launch_xy_w<TW, true>(s, st) : launch_xy_w<TW, false>(s, st);
 }
 
 template <int TW, bool WIDE, int NTZ>
-int launch_z_t(const edt_grid_t* g, int32_t* d2, int32_t* site, hipStream_t st)
+int launch_z_t(const EdtMapSet& s, hipStream_t st)
 {
     static bool done = false;
     int rc = allow_lds(k_edt_z<TW, WIDE, NTZ>, done);
     if (rc) return rc;
-    const int ntx = (g->nx + TW - 1) / TW;
-    const size_t lds = z_lds(TW, g->nz, NTZ);
-    hipLaunchKernelGGL((k_edt_z<TW, WIDE, NTZ>), dim3(g->ny * ntx), dim3(NTZ), lds, st, d2, site,
-                       g->nx, g->ny, g->nz, ntx);
+    hipLaunchKernelGGL((k_edt_z<TW, WIDE, NTZ>), dim3(s.total), dim3(NTZ), z_lds(TW, s.nz_max, NTZ), st,
+                       s);
     return check_launch("k_edt_z");
 }
 
 template <int TW, int NTZ>
-int launch_z_tw(const edt_grid_t* g, int32_t* d2, int32_t* site, bool wide, hipStream_t st)
+int launch_z_tw(const EdtMapSet& s, hipStream_t st)
 {
-    return wide ? launch_z_t<TW, true, NTZ>(g, d2, site, st) : launch_z_t<TW, false, NTZ>(g, d2, site, st);
+    return s.wide ? launch_z_t<TW, true, NTZ>(s, st) : launch_z_t<TW, false, NTZ>(s, st);
+}
+
+// The tiles of every map of the set, ntx column tiles of width tw per row
+// of the pass (rows: z slices for xy, y rows for z).
+void fill_set(const edt_batch_map_t* maps, int n, int tw, bool z_pass, EdtMapSet& s)
+{
+    s.n = n;
+    s.total = 0;
+    s.ny_max = s.nz_max = 0;
+    s.wide = false;
+    for (int i = 0; i < n; ++i) {
+        const edt_grid_t& g = maps[i].grid;
+        EdtMap& d = s.m[i];
+        d.occ = maps[i].occ;
+        d.d2 = maps[i].d2;
+        d.site = maps[i].site;
+        d.nx = g.nx;
+        d.ny = g.ny;
+        d.nz = g.nz;
+        d.ntx = (g.nx + tw - 1) / tw;
+        d.begin = s.total;
+        s.total += (z_pass ? g.ny : g.nz) * d.ntx;
+        s.ny_max = std::max(s.ny_max, g.ny);
+        s.nz_max = std::max(s.nz_max, g.nz);
+        s.wide = s.wide || needs_wide(&g);
+    }
 }
 
 }  // namespace
@@ -112,44 +145,101 @@ EdtTuning default_tuning(const edt_grid_t* g)
     return t;
 }
 
-int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st)
+int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMapSet& xy,
+                  EdtMapSet& z)
 {
-    const bool wide = needs_wide(g);
+    if (!maps || n < 1 || n > EDT_BATCH_MAX) {
+        set_error("need 1..%d maps, got %d", EDT_BATCH_MAX, n);
+        return EDT_ERR_ARG;
+    }
+    edt_grid_t big{};
+    big.voxel = 1.0f;
+    for (int i = 0; i < n; ++i) {
+        const edt_grid_t* g = &maps[i].grid;
+        int rc = check_grid(g);
+        if (rc) return rc;
+        if (!maps[i].occ || !maps[i].d2 || !maps[i].site) {
+            set_error("map %d: NULL occ, d2 or site", i);
+            return EDT_ERR_ARG;
+        }
+        big.nx = std::max(big.nx, g->nx);
+        big.ny = std::max(big.ny, g->ny);
+        big.nz = std::max(big.nz, g->nz);
+    }
+    if (!tile_ok(1, t.xy_tw, &big, 256) || !tile_ok(2, t.z_tw, &big, t.z_nt)) {
+        set_error("tiles (%d, %d / %d) not valid for maps up to %d x %d x %d", t.xy_tw, t.z_tw, t.z_nt,
+                  big.nx, big.ny, big.nz);
+        return EDT_ERR_UNSUPPORTED;
+    }
+    fill_set(maps, n, t.xy_tw, false, xy);
+    fill_set(maps, n, t.z_tw, true, z);
+    return EDT_OK;
+}
+
+int launch_edt_xy_set(const EdtMapSet& s, int tw, hipStream_t st)
+{
     switch (tw) {
-        case 64: return launch_xy_tw<64>(g, occ, xy, wide, st);
-        case 32: return launch_xy_tw<32>(g, occ, xy, wide, st);
-        case 16: return launch_xy_tw<16>(g, occ, xy, wide, st);
+        case 64: return launch_xy_tw<64>(s, st);
+        case 32: return launch_xy_tw<32>(s, st);
+        case 16: return launch_xy_tw<16>(s, st);
         default: set_error("bad xy tile width %d", tw); return EDT_ERR_ARG;
     }
 }
 
-int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st)
+int launch_edt_z_set(const EdtMapSet& s, int tw, int nt, hipStream_t st)
 {
-    const bool wide = needs_wide(g);
     if (nt == 256) {
         switch (tw) {
-            case 64: return launch_z_tw<64, 256>(g, d2, site, wide, st);
-            case 32: return launch_z_tw<32, 256>(g, d2, site, wide, st);
-            case 16: return launch_z_tw<16, 256>(g, d2, site, wide, st);
-            case 8: return launch_z_tw<8, 256>(g, d2, site, wide, st);
+            case 64: return launch_z_tw<64, 256>(s, st);
+            case 32: return launch_z_tw<32, 256>(s, st);
+            case 16: return launch_z_tw<16, 256>(s, st);
+            case 8: return launch_z_tw<8, 256>(s, st);
         }
     } else if (nt == 128) {
         switch (tw) {
-            case 64: return launch_z_tw<64, 128>(g, d2, site, wide, st);
-            case 32: return launch_z_tw<32, 128>(g, d2, site, wide, st);
-            case 16: return launch_z_tw<16, 128>(g, d2, site, wide, st);
-            case 8: return launch_z_tw<8, 128>(g, d2, site, wide, st);
+            case 64: return launch_z_tw<64, 128>(s, st);
+            case 32: return launch_z_tw<32, 128>(s, st);
+            case 16: return launch_z_tw<16, 128>(s, st);
+            case 8: return launch_z_tw<8, 128>(s, st);
         }
     } else if (nt == 64) {
         switch (tw) {
-            case 64: return launch_z_tw<64, 64>(g, d2, site, wide, st);
-            case 32: return launch_z_tw<32, 64>(g, d2, site, wide, st);
-            case 16: return launch_z_tw<16, 64>(g, d2, site, wide, st);
-            case 8: return launch_z_tw<8, 64>(g, d2, site, wide, st);
+            case 64: return launch_z_tw<64, 64>(s, st);
+            case 32: return launch_z_tw<32, 64>(s, st);
+            case 16: return launch_z_tw<16, 64>(s, st);
+            case 8: return launch_z_tw<8, 64>(s, st);
         }
     }
     set_error("bad z tile %d / group %d", tw, nt);
     return EDT_ERR_ARG;
+}
+
+namespace {
+edt_batch_map_t one_map(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, int32_t* site)
+{
+    edt_batch_map_t m{};
+    m.grid = *g;
+    m.occ = occ;
+    m.d2 = d2;
+    m.site = site;
+    return m;
+}
+}  // namespace
+
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st)
+{
+    const edt_batch_map_t m = one_map(g, occ, nullptr, reinterpret_cast<int32_t*>(xy));
+    EdtMapSet s;
+    fill_set(&m, 1, tw, false, s);
+    return launch_edt_xy_set(s, tw, st);
+}
+
+int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st)
+{
+    const edt_batch_map_t m = one_map(g, nullptr, d2, site);
+    EdtMapSet s;
+    fill_set(&m, 1, tw, true, s);
+    return launch_edt_z_set(s, tw, nt, st);
 }
 
 }  // namespace edtmi

@@ -16,12 +16,20 @@ from . import edt
 
 
 class ControlCycle:
+    EDT_MODES = ("many", "per_map", "batched")
+
     def __init__(self, ci, device="cuda:0", self_mask: int = 0xFF, centres=None,
-                 batched_edt: bool = False):
+                 edt_mode: str = "many", two_streams: bool = False):
         """ci: inputs.CycleInputs.  centres: float32 [S, m, 3] per joint
         state (computed from ci.joint_states by forward kinematics if None).
-        batched_edt: compute both maps' EDTs in one persistent batched launch
-        instead of one edt_compute per map (same results)."""
+        edt_mode: how the two maps' EDTs run (same results every way):
+          "many"     one edt_compute_many for both maps (one launch per pass,
+                     the second map's tiles fill the first one's tail);
+          "per_map"  one edt_compute per map;
+          "batched"  one persistent edt_compute_batched launch.
+        two_streams ("per_map" only): run the environment map's steps on a
+        second stream forked from and joined back into the caller's stream;
+        the point insertion still waits for the self map it excludes."""
         from . import inputs
         self.ci = ci
         self.grid = ci.grid
@@ -52,10 +60,18 @@ class ControlCycle:
         self.out_self = edt.new_query_out(m, d)
         self.n_frames = self.frames.shape[0]
         self.n_states = self.poses.shape[0]
-        self.batched_edt = bool(batched_edt)
-        if self.batched_edt:
-            self.maps = edt.batch_maps([ci.grid, ci.grid], [self.occ_env, self.occ_self],
-                                       [self.d2_env, self.d2_self], [self.site_env, self.site_self])
+        if edt_mode not in self.EDT_MODES:
+            raise ValueError(f"edt_mode must be one of {self.EDT_MODES}")
+        self.edt_mode = edt_mode
+        self.two_streams = bool(two_streams) and edt_mode == "per_map"
+        if self.two_streams:
+            self.side = torch.cuda.Stream(device=d)
+            self.ev_fork = torch.cuda.Event()
+            self.ev_links = torch.cuda.Event()
+            self.ev_join = torch.cuda.Event()
+        self.maps = edt.batch_maps([ci.grid, ci.grid], [self.occ_env, self.occ_self],
+                                   [self.d2_env, self.d2_self], [self.site_env, self.site_self])
+        if edt_mode == "batched":
             self.batch_ws = edt.new_batch_workspace(2, d)
 
     @property
@@ -64,6 +80,8 @@ class ControlCycle:
 
     def run(self, k: int, stream=None):
         """Enqueue cycle k (frame k mod F, joint state k mod S)."""
+        if self.two_streams:
+            return self._run_two_streams(k, stream)
         g = self.grid
         f = k % self.n_frames
         s = k % self.n_states
@@ -73,7 +91,9 @@ class ControlCycle:
                              self.self_mask, stream)
         edt.edt_insert_points(g, self.occ_env, self.frames[f], self.T, exclude=self.occ_self,
                               stream=stream)
-        if self.batched_edt:
+        if self.edt_mode == "many":
+            edt.edt_compute_many(self.maps, stream=stream)
+        elif self.edt_mode == "batched":
             edt.edt_compute_batched(self.maps, self.batch_ws, stream=stream)
         else:
             edt.edt_compute(g, self.occ_env, self.d2_env, self.site_env, stream=stream)
@@ -82,6 +102,33 @@ class ControlCycle:
                               self.out_env, stream)
         edt.edt_query_spheres(g, self.d2_self, self.site_self, self.centres[s], self.radii,
                               self.out_self, stream)
+
+    def _run_two_streams(self, k: int, stream=None):
+        g = self.grid
+        f = k % self.n_frames
+        s = k % self.n_states
+        main = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        side = self.side
+        self.ev_fork.record(main)
+        side.wait_event(self.ev_fork)
+        # self map on the caller's stream
+        edt.edt_clear(g, self.occ_self, main)
+        edt.edt_insert_links(g, self.occ_self, self.link_pts, self.link_off, self.poses[s],
+                             self.self_mask, main)
+        self.ev_links.record(main)
+        # environment map on the side stream, its insertion after the links
+        edt.edt_clear(g, self.occ_env, side)
+        side.wait_event(self.ev_links)
+        edt.edt_insert_points(g, self.occ_env, self.frames[f], self.T, exclude=self.occ_self,
+                              stream=side)
+        edt.edt_compute(g, self.occ_env, self.d2_env, self.site_env, stream=side)
+        edt.edt_query_spheres(g, self.d2_env, self.site_env, self.centres[s], self.radii,
+                              self.out_env, side)
+        edt.edt_compute(g, self.occ_self, self.d2_self, self.site_self, stream=main)
+        edt.edt_query_spheres(g, self.d2_self, self.site_self, self.centres[s], self.radii,
+                              self.out_self, main)
+        self.ev_join.record(side)
+        main.wait_event(self.ev_join)
 
     def capture_graphs(self, n_graphs: int):
         """One HIP graph per (frame, state) slot k < n_graphs, each replaying

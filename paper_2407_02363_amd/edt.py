@@ -56,6 +56,7 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_insert_points", "edt_insert_links", "edt_workspace_bytes", "edt_compute",
             "edt_query_spheres", "edt_compute_stage", "edt_default_tuning", "edt_compute_tuned",
             "edt_autotune", "edt_batch_workspace_bytes", "edt_compute_batched", "edt_batch_status",
+            "edt_compute_many",
             "edt_autotune_batched"]
 
 BATCH_MAX = 48
@@ -91,6 +92,7 @@ def lib():
                          ctypes.c_int),
         "edt_batch_workspace_bytes": ([i32], ctypes.c_size_t),
         "edt_compute_batched": ([P, i32, P, ctypes.c_size_t, ctypes.POINTER(Tuning), P], ctypes.c_int),
+        "edt_compute_many": ([P, i32, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_batch_status": ([P, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
         "edt_autotune_batched": ([P, i32, P, ctypes.c_size_t, i32, ctypes.POINTER(Tuning),
                                   ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
@@ -274,6 +276,13 @@ def edt_batch_workspace_bytes(n_maps: int) -> int:
 
 def new_batch_workspace(n_maps: int, device="cuda"):
     return torch.empty(edt_batch_workspace_bytes(n_maps), dtype=torch.uint8, device=device)
+
+
+def edt_compute_many(maps, tuning=None, stream=None):
+    """maps: result of batch_maps(); one xy and one z launch for all maps."""
+    _check(lib().edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), len(maps), _tuning(tuning),
+                                  _stream(stream)),
+           "edt_compute_many")
 
 
 def edt_compute_batched(maps, ws, tuning=None, stream=None):

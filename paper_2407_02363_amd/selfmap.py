@@ -4,7 +4,9 @@ For each state (Alg. 2 lines for the self map): ClearMap, insert the voxel
 models of the obstacle links O_L placed by the state's forward kinematics,
 compute the exact EDT, and read sqrt(d2) at every sphere centre
 (ExtractClosestObstaclePose).  States go in chunks of up to EDT_BATCH_MAX
-maps: one persistent batched EDT launch per chunk, and the whole chunk is
+maps: one edt_compute_many per chunk (one launch per pass over every map of
+the chunk; edt_mode="batched" uses the persistent batched launch), and the
+whole chunk is
 replayed from a HIP graph whose pose and centre buffers are refilled before
 every replay.  Graphs exist for chunk sizes 1, 2, 4, ... and the full
 chunk, so a partial chunk (the states the surrogate could not clear, for
@@ -22,7 +24,10 @@ from . import edt, inputs
 
 class SelfMapLabeler:
     def __init__(self, setup: "inputs.SelfMapSetup", chunk: int = 48, device="cuda:0",
-                 use_graph: bool = True):
+                 use_graph: bool = True, edt_mode: str = "many"):
+        if edt_mode not in ("many", "batched"):
+            raise ValueError("edt_mode must be 'many' or 'batched'")
+        self.edt_mode = edt_mode
         self.s = setup
         self.chunk = int(chunk)
         self.dev = torch.device(device)
@@ -68,7 +73,10 @@ class SelfMapLabeler:
             edt.edt_clear(g, self.occ[i], stream)
             edt.edt_insert_links(g, self.occ[i], self.link_pts, self.s.link_off, self.poses[i],
                                  self.s.mask, stream)
-        edt.edt_compute_batched(self.maps[k], self.ws, stream=stream)
+        if self.edt_mode == "many":
+            edt.edt_compute_many(self.maps[k], stream=stream)
+        else:
+            edt.edt_compute_batched(self.maps[k], self.ws, stream=stream)
         for i in range(k):
             edt.edt_query_spheres(g, self.d2[i], self.site[i], self.centres[i], self.radii,
                                   self.out[i], stream)

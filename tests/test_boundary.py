@@ -88,6 +88,15 @@ def test_host_validation_rejects_bad_arguments(lib):
                                  None) == -5
     bad_t = edt.Tuning(24, 8)
     assert lib.edt_compute_tuned(ctypes.byref(ok), one, one, one, ctypes.byref(bad_t), None) == -5
+    # edt_compute_many: map count, NULL buffers and tiles are checked before any launch
+    maps = (edt.BatchMap * 49)()
+    for m in maps:
+        m.grid, m.occ, m.d2, m.site = ok, 256, 256, 256
+    assert lib.edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), 0, None, None) == -1
+    assert lib.edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), 49, None, None) == -1
+    assert lib.edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), 2, ctypes.byref(bad_t), None) == -5
+    maps[1].d2 = None
+    assert lib.edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), 2, ctypes.byref(bad_t), None) == -1
     huge = edt.EdtGrid(8, 1024, 8, (ctypes.c_float * 3)(0, 0, 0), 0.01)
     assert lib.edt_compute_tuned(ctypes.byref(huge), one, one, one,
                                  ctypes.byref(edt.Tuning(64, 8)), None) == -5

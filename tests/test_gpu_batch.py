@@ -158,6 +158,16 @@ def test_batch_cycle_plain_batched_graph(oracle_lib):
     say("[batch cycle] batched")
     bc.run_batched()
     verify("batched")
+    say("[batch cycle] many")
+    for t in bc.d2 + bc.site:
+        t.fill_(-7)
+    bc.run_many()
+    verify("many")
+    graph_many = bc.capture(bc.run_many)
+    for t in bc.d2 + bc.site:
+        t.fill_(-7)
+    graph_many.replay()
+    verify("many graph")
     graph = bc.capture(bc.run_batched)
     for rep in range(3):
         for t in bc.d2 + bc.site:
@@ -167,3 +177,41 @@ def test_batch_cycle_plain_batched_graph(oracle_lib):
         verify(f"graph {rep}")
         bc.run_plain()
         torch.cuda.synchronize()
+
+
+def run_many(occs, grids, tuning=None):
+    d = dev()
+    o = [torch.from_numpy(np.ascontiguousarray(x).ravel()).to(d) for x in occs]
+    d2 = [torch.full((x.size,), -7, dtype=torch.int32, device=d) for x in occs]
+    st = [torch.full((x.size,), -7, dtype=torch.int32, device=d) for x in occs]
+    maps = edt.batch_maps(grids, o, d2, st)
+    edt.edt_compute_many(maps, tuning)
+    torch.cuda.synchronize()
+    return ([a.cpu().numpy().reshape(x.shape) for a, x in zip(d2, occs)],
+            [a.cpu().numpy().reshape(x.shape) for a, x in zip(st, occs)])
+
+
+@pytest.mark.parametrize("tiles", [None, (16, 8, 256), (32, 32, 128), (64, 16, 64), (32, 64, 256)])
+def test_many_matches_oracle(oracle_lib, tiles):
+    """One launch per pass over maps of different shapes (a map with an axis
+    above 512 takes every map onto the 64-bit envelope test)."""
+    occs, grids = mixed_batch(3)
+    if tiles is None:
+        occs.append(inputs.random_grid((6, 9, 700), 0.01, 77))
+        grids.append(inputs.Grid(700, 9, 6))
+    say(f"[many] {len(occs)} maps tiles {tiles}")
+    d2s, sites = run_many(occs, grids, tiles)
+    check(occs, d2s, sites, oracle_lib, f"many {tiles}")
+
+
+def test_many_equals_one_call_per_map():
+    """48 maps of one shape (the self-map labeler's case): identical to one
+    edt_compute per map."""
+    sh = (24, 40, 36)
+    occs = [inputs.random_grid(sh, 0.003 * (1 + i % 5), 500 + i) for i in range(edt.BATCH_MAX)]
+    grids = [inputs.Grid(sh[2], sh[1], sh[0])] * len(occs)
+    d2s, sites = run_many(occs, grids)
+    from tests.gpu_util import gpu_edt
+    for i in (0, 1, 17, 47):
+        rd2, rs = gpu_edt(occs[i])
+        assert np.array_equal(d2s[i], rd2) and np.array_equal(sites[i], rs), i

@@ -37,12 +37,13 @@ def gpu_state(cyc):
 NAMES = ["occ_self", "occ_env", "d2_env", "site_env", "d2_self", "site_self", "q_env", "q_self"]
 
 
-@pytest.mark.parametrize("batched_edt", [False, True])
-def test_cycle_matches_oracle(oracle_lib, batched_edt):
+@pytest.mark.parametrize("variant", ["many", "per_map", "batched", "two_streams"])
+def test_cycle_matches_oracle(oracle_lib, variant):
     ci = inputs.cycle_inputs(4, n_frames=2, n_states=3)
-    cyc = ControlCycle(ci, "cuda:0", batched_edt=batched_edt)
+    cyc = ControlCycle(ci, "cuda:0", edt_mode="per_map" if variant == "two_streams" else variant,
+                       two_streams=variant == "two_streams")
     for k in range(3):
-        say(f"[cycle] k={k} batched_edt={batched_edt}")
+        say(f"[cycle] k={k} {variant}")
         cyc.run(k)
         torch.cuda.synchronize()
         got = gpu_state(cyc)
@@ -51,9 +52,11 @@ def test_cycle_matches_oracle(oracle_lib, batched_edt):
             assert np.array_equal(a, b), f"cycle {k}: {name} differs"
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("variant", ["many", "two_streams"])
+def test_graph_replays_match_eager(variant):
     ci = inputs.cycle_inputs(5, n_frames=2, n_states=2)
-    cyc = ControlCycle(ci, "cuda:0")
+    cyc = ControlCycle(ci, "cuda:0", edt_mode="per_map" if variant == "two_streams" else variant,
+                       two_streams=variant == "two_streams")
     say("[cycle graph] capture")
     graphs = cyc.capture_graphs(2)
     eager = []

@@ -232,10 +232,11 @@ def test_gather_and_clip_match_plain():
     assert np.isnan(yb[3]).all() and np.array_equal(np.delete(yb, 3, 0), np.delete(y2.cpu().numpy(), 3, 0))
 
 
-def test_labeler_matches_oracle(oracle_lib):
+@pytest.mark.parametrize("edt_mode", ["many", "batched"])
+def test_labeler_matches_oracle(oracle_lib, edt_mode):
     from paper_2407_02363_amd.selfmap import SelfMapLabeler
     st = inputs.self_map_setup()
-    lab = SelfMapLabeler(st, chunk=8, device=dev())
+    lab = SelfMapLabeler(st, chunk=8, device=dev(), edt_mode=edt_mode)
     qs = inputs.random_joint_states(13, 11)   # one full chunk and a partial one
     say("[mlp] labels")
     got = lab.labels(qs).cpu().numpy()
