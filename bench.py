@@ -10,8 +10,10 @@ in both.  Inputs are resident in device memory before timing starts.
 Printed as one JSON line:
   value        EDT voxels per second over whole cycles (2 maps per cycle),
                in Mvoxels/s -- insert, clear and query time included; each
-               cycle is one HIP-graph replay (timing "graph"; the eager
-               rate, one library call per step, is under "eager").
+               cycle runs the two maps on two streams from three HIP
+               graphs ("timing"); the eager one-stream rate is under
+               "eager" and the other ways of running it under
+               "cycle_variants".
   latency      p50 / p99 of the per-cycle latency over >= 1000 cycles, host
                clock from enqueue to the sphere results landing in host
                memory, plain per-map launches and graph-replayed cycles.
@@ -387,7 +389,7 @@ def main():
         del src, dst
     log("[bench] generating inputs")
     ci = inputs.cycle_inputs(0, n_frames=args.frames, n_states=args.states)
-    cyc = ControlCycle(ci, dev, edt_mode="many")
+    cyc = ControlCycle(ci, dev, edt_mode="per_map")
     g = ci.grid
     st = torch.cuda.current_stream()
 
@@ -404,33 +406,36 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
-    # ---- throughput: K cycles back to back, eager (one library call per step
-    # of the cycle) and replayed from HIP graphs (one replay per cycle)
+    # ---- throughput: K cycles back to back.  Eager: one library call per
+    # step of the cycle on one stream.  Headline: the two maps on two streams,
+    # each cycle replayed from three single-stream HIP graphs (self-map
+    # insertion; the whole environment map on a second stream; the self-map
+    # transform and query), so the two maps' kernels overlap.
     log(f"[bench] timing {args.steps} eager cycles")
     el_eager = run_steps(cyc.run, args.steps)
     eager = {"ms_per_cycle": 1e3 * el_eager / args.steps,
              "mvox_s": cyc.voxels_per_cycle * args.steps / el_eager / 1e6}
-    graphs = None
-    if args.graphs > 0:
-        log(f"[bench] capturing {args.graphs} cycle graphs")
-        graphs = cyc.capture_graphs(args.graphs)
-        # check the replayed cycle against an eager run of the same slot
+    split = args.graphs > 0
+    if split:
+        log(f"[bench] capturing {args.graphs} split cycle graphs")
         cyc.run(1)
         torch.cuda.synchronize()
-        ref = (cyc.d2_env.clone(), cyc.site_env.clone(), cyc.out_env.clone(), cyc.out_self.clone())
-        graphs[1].replay()
+        ref = [t.clone() for t in (cyc.d2_env, cyc.site_env, cyc.d2_self, cyc.site_self,
+                                   cyc.out_env, cyc.out_self)]
+        cyc.capture_split_graphs(args.graphs)
+        cyc.replay_split(1)
         torch.cuda.synchronize()
-        same = all(torch.equal(a, b) for a, b in
-                   zip(ref, (cyc.d2_env, cyc.site_env, cyc.out_env, cyc.out_self)))
-        if not same:
-            raise SystemExit("graph replay differs from the eager cycle")
+        if not all(torch.equal(a, b) for a, b in
+                   zip(ref, (cyc.d2_env, cyc.site_env, cyc.d2_self, cyc.site_self, cyc.out_env,
+                             cyc.out_self))):
+            raise SystemExit("split-graph replay differs from the eager cycle")
         for k in range(args.warmup):
-            graphs[k % len(graphs)].replay()
-        log(f"[bench] timing {args.steps} graph-replayed cycles")
-        el = run_steps(lambda k: graphs[k % len(graphs)].replay(), args.steps)
-        mode = "graph"
+            cyc.replay_split(k)
+        log(f"[bench] timing {args.steps} graph-replayed two-stream cycles")
+        el = run_steps(cyc.replay_split, args.steps)
+        mode = "two streams, three graphs per cycle"
     else:
-        el, mode = el_eager, "eager"
+        el, mode = el_eager, "eager, one stream"
     ms_per_step = 1e3 * el / args.steps
     value = cyc.voxels_per_cycle * args.steps / el / 1e6
 
@@ -453,14 +458,15 @@ def main():
     lat_plain = latency_run(cyc.run, args.latency_cycles)
     latency = {"plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
                          "cycles": len(lat_plain)}}
-    if graphs is not None:
-        lat_graph = latency_run(lambda k: graphs[k % len(graphs)].replay(), args.latency_cycles)
+    if split:
+        lat_graph = latency_run(cyc.replay_split, args.latency_cycles)
         latency["graph"] = {"p50_ms": pct(lat_graph, 50), "p99_ms": pct(lat_graph, 99),
                             "cycles": len(lat_graph)}
 
     # ---- the same cycle with the EDTs run other ways (identical results)
     variants = {}
-    for name, kw in (("per_map", {"edt_mode": "per_map"}),
+    for name, kw in (("many_one_stream", {"edt_mode": "many"}),
+                     ("per_map_one_stream", {"edt_mode": "per_map"}),
                      ("per_map_two_streams", {"edt_mode": "per_map", "two_streams": True}),
                      ("batched_persistent", {"edt_mode": "batched"})):
         log(f"[bench] cycle variant {name}")

@@ -130,6 +130,69 @@ class ControlCycle:
         self.ev_join.record(side)
         main.wait_event(self.ev_join)
 
+    # -- the two-stream cycle replayed from three single-stream graphs per
+    # slot: [clear + insert the self map] on the caller's stream, then
+    # [clear, insert, EDT, query of the environment map] on the side stream
+    # once the self map is in, and [EDT, query of the self map] on the
+    # caller's stream, which finally waits for the side stream.
+    def _self_links(self, s, stream=None):
+        edt.edt_clear(self.grid, self.occ_self, stream)
+        edt.edt_insert_links(self.grid, self.occ_self, self.link_pts, self.link_off, self.poses[s],
+                             self.self_mask, stream)
+
+    def _env_all(self, f, s, stream=None):
+        g = self.grid
+        edt.edt_clear(g, self.occ_env, stream)
+        edt.edt_insert_points(g, self.occ_env, self.frames[f], self.T, exclude=self.occ_self,
+                              stream=stream)
+        edt.edt_compute(g, self.occ_env, self.d2_env, self.site_env, stream=stream)
+        edt.edt_query_spheres(g, self.d2_env, self.site_env, self.centres[s], self.radii,
+                              self.out_env, stream)
+
+    def _self_edt(self, s, stream=None):
+        g = self.grid
+        edt.edt_compute(g, self.occ_self, self.d2_self, self.site_self, stream=stream)
+        edt.edt_query_spheres(g, self.d2_self, self.site_self, self.centres[s], self.radii,
+                              self.out_self, stream)
+
+    def capture_split_graphs(self, n_graphs: int):
+        """Three graphs per slot k < n_graphs (see replay_split)."""
+        if not hasattr(self, "side"):
+            self.side = torch.cuda.Stream(device=self.dev)
+            self.ev_links = torch.cuda.Event()
+            self.ev_join = torch.cuda.Event()
+        torch.cuda.synchronize(self.dev)
+        parts = []
+        for k in range(n_graphs):
+            f, s = k % self.n_frames, k % self.n_states
+            trio = []
+            for fn in (lambda: self._self_links(s), lambda: self._env_all(f, s),
+                       lambda: self._self_edt(s)):
+                fn()
+                torch.cuda.synchronize(self.dev)
+                gr = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gr, capture_error_mode="thread_local"):
+                    fn()
+                trio.append(gr)
+            parts.append(tuple(trio))
+        torch.cuda.synchronize(self.dev)
+        self.split_graphs = parts
+        return parts
+
+    def replay_split(self, k: int):
+        """Cycle k from the split graphs, on the current stream plus the side
+        stream (joined back before returning)."""
+        g_links, g_env, g_self = self.split_graphs[k % len(self.split_graphs)]
+        main = torch.cuda.current_stream(self.dev)
+        g_links.replay()
+        self.ev_links.record(main)
+        self.side.wait_event(self.ev_links)
+        with torch.cuda.stream(self.side):
+            g_env.replay()
+        self.ev_join.record(self.side)
+        g_self.replay()
+        main.wait_event(self.ev_join)
+
     def capture_graphs(self, n_graphs: int):
         """One HIP graph per (frame, state) slot k < n_graphs, each replaying
         the whole cycle k; warm-up runs first so nothing initialises inside

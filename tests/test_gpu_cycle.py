@@ -75,3 +75,24 @@ def test_graph_replays_match_eager(variant):
                 assert np.array_equal(a, b), f"replay {rep} slot {k}: {name} differs"
             cyc.run(1 - k)
             torch.cuda.synchronize()
+
+
+def test_split_graph_replays_match_eager():
+    """The two-stream cycle replayed from three graphs per slot gives the
+    eager cycle's bytes, replay after replay."""
+    ci = inputs.cycle_inputs(6, n_frames=2, n_states=2)
+    cyc = ControlCycle(ci, "cuda:0", edt_mode="per_map")
+    eager = []
+    for k in range(2):
+        cyc.run(k)
+        torch.cuda.synchronize()
+        eager.append(gpu_state(cyc))
+    say("[cycle split graphs] capture")
+    cyc.capture_split_graphs(2)
+    for rep in range(3):
+        for k in (1, 0):
+            say(f"[cycle split graphs] replay {rep} slot {k}")
+            cyc.replay_split(k)
+            torch.cuda.synchronize()
+            for name, a, b in zip(NAMES, gpu_state(cyc), eager[k]):
+                assert np.array_equal(a, b), f"replay {rep} slot {k}: {name} differs"
