@@ -10,6 +10,8 @@ Functions (each cites the paper passage it follows in its docstring):
   insert_points(...)    point-cloud insertion (Sec. III-A)
   insert_links(...)     link voxel models placed by joint state (Sec. III-A)
   query_spheres(...)    closest obstacle at sphere centres (Alg. 2, Eq. dist)
+  update_logodds(...)   per-frame Bayesian occupancy update (Sec. III-A)
+  ray_walk(a, b)        voxels a sensor ray crosses (the update's traversal)
 """
 from __future__ import annotations
 
@@ -58,6 +60,11 @@ def _load():
                                                                    ctypes.c_int, P]
         lib.oracle_query_spheres.restype = None
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_ray_walk.argtypes = [P, P, P, ctypes.c_int]
+        lib.oracle_ray_walk.restype = ctypes.c_int
+        lib.oracle_update_logodds.argtypes = ([ctypes.c_int] * 3 + [P, ctypes.c_float, P, P, P,
+                                              ctypes.c_int64, P, P] + [ctypes.c_int] * 5)
+        lib.oracle_update_logodds.restype = None
         _lib = lib
     return _lib
 
@@ -134,3 +141,37 @@ def query_spheres(grid, d2: np.ndarray, site: np.ndarray, centres: np.ndarray,
     _load().oracle_query_spheres(nx, ny, nz, _ptr(origin), v, _ptr(d2), _ptr(site), _ptr(c),
                                  _ptr(r), c.shape[0], _ptr(out))
     return out
+
+
+def ray_walk(a, b) -> np.ndarray:
+    """Voxels (int32 [k, 3]) the ray from a to b (voxel units) crosses, from
+    floor(a) to floor(b), one voxel per step (Amanatides-Woo order)."""
+    a = np.ascontiguousarray(a, np.float32).reshape(3)
+    b = np.ascontiguousarray(b, np.float32).reshape(3)
+    cap = int(np.abs(np.floor(b) - np.floor(a)).sum()) + 1
+    out = np.zeros((cap, 3), np.int32)
+    steps = _load().oracle_ray_walk(_ptr(a), _ptr(b), _ptr(out), cap)
+    assert steps + 1 == cap
+    return out
+
+
+# log-odds parameters in hundredths of a nat: P(hit) 0.7, P(miss) 0.4,
+# clamped to [-2.0, 3.5], occupied above 0 (probability above one half)
+LOGODDS_DEFAULT = dict(hit=85, miss=-41, lmin=-200, lmax=350, threshold=0)
+
+
+def update_logodds(grid, logodds: np.ndarray, occ: np.ndarray, pts: np.ndarray, T: np.ndarray,
+                   exclude: np.ndarray | None = None, hit=85, miss=-41, lmin=-200, lmax=350,
+                   threshold=0):
+    """One frame's Bayesian occupancy update (Sec. III-A), in place on the
+    int16 log-odds grid; occ (uint8) becomes logodds > threshold."""
+    nx, ny, nz, origin, v = _grid_args(grid)
+    pts = np.ascontiguousarray(pts, np.float32).reshape(-1, 3)
+    T = np.ascontiguousarray(T, np.float32).reshape(12)
+    assert logodds.dtype == np.int16 and logodds.flags.c_contiguous and logodds.size == grid.n
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous and occ.size == grid.n
+    ex = None if exclude is None else np.ascontiguousarray(exclude, np.uint8)
+    _load().oracle_update_logodds(nx, ny, nz, _ptr(origin), v, _ptr(logodds), _ptr(occ), _ptr(pts),
+                                  pts.shape[0], _ptr(T), None if ex is None else _ptr(ex),
+                                  int(hit), int(miss), int(lmin), int(lmax), int(threshold))
+    return logodds, occ

@@ -334,3 +334,143 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Probabilistic occupancy (Sec. III-A: each point's voxel has its          */
+/* occupancy updated as a Bayesian process).  Per frame, in log-odds:       */
+/* a voxel holding at least one endpoint gets one hit update, a voxel that  */
+/* some sensor ray crosses on its way to an endpoint (and that holds no     */
+/* endpoint) gets one miss update, each clamped to [lmin, lmax]; the voxel  */
+/* is occupied iff its log-odds exceed the threshold.  Only points whose    */
+/* endpoint voxel lies in the map and is not excluded take part.           */
+/*                                                                          */
+/* The ray from the sensor voxel to the endpoint voxel is walked one voxel  */
+/* at a time (the incremental traversal of Amanatides and Woo): in voxel    */
+/* units a = (s - origin) / voxel, b = (p - origin) / voxel, d = b - a; an  */
+/* axis with voxels left to cross has its next boundary crossing at         */
+/* tmax = (boundary - a) / d, growing by 1 / |d| per crossing; every step   */
+/* crosses on the axis with the smallest tmax (x before y before z on       */
+/* ties) among those with voxels left, so the walk ends exactly on the      */
+/* endpoint voxel after |dx| + |dy| + |dz| steps.  float32, one rounding    */
+/* per operation in this order.                                             */
+/* ------------------------------------------------------------------------ */
+static inline int64_t lin3(int x, int y, int z, int nx, int ny)
+{
+    return x + (int64_t)nx * (y + (int64_t)ny * z);
+}
+
+/* Voxels from the start voxel to (excluding) the end voxel; returns the
+ * number of steps, writes up to max_out voxels (x, y, z triples) of the
+ * walk including the end voxel. */
+int oracle_ray_walk(const float* a, const float* b, int32_t* out, int max_out)
+{
+    int cur[3], end[3], step[3], left[3];
+    float tmax[3], tdel[3];
+    int total = 0;
+    for (int i = 0; i < 3; ++i) {
+        cur[i] = (int)floorf(a[i]);
+        end[i] = (int)floorf(b[i]);
+        const float d = b[i] - a[i];
+        step[i] = end[i] > cur[i] ? 1 : (end[i] < cur[i] ? -1 : 0);
+        left[i] = step[i] > 0 ? end[i] - cur[i] : cur[i] - end[i];
+        total += left[i];
+        if (step[i] != 0) {
+            const float bound = (float)(step[i] > 0 ? cur[i] + 1 : cur[i]);
+            tmax[i] = (bound - a[i]) / d;
+            tdel[i] = 1.0f / fabsf(d);
+        } else {
+            tmax[i] = INFINITY;
+            tdel[i] = 0.0f;
+        }
+    }
+    int n = 0;
+    if (n < max_out) {
+        out[3 * n + 0] = cur[0]; out[3 * n + 1] = cur[1]; out[3 * n + 2] = cur[2];
+    }
+    ++n;
+    for (int k = 0; k < total; ++k) {
+        int ax = -1;
+        for (int i = 0; i < 3; ++i)
+            if (left[i] > 0 && (ax < 0 || tmax[i] < tmax[ax])) ax = i;
+        cur[ax] += step[ax];
+        left[ax] -= 1;
+        tmax[ax] = tmax[ax] + tdel[ax];
+        if (n < max_out) {
+            out[3 * n + 0] = cur[0]; out[3 * n + 1] = cur[1]; out[3 * n + 2] = cur[2];
+        }
+        ++n;
+    }
+    return total;
+}
+
+void oracle_update_logodds(int nx, int ny, int nz, const float* origin, float voxel,
+                           int16_t* logodds, uint8_t* occ, const float* pts, int64_t n,
+                           const float* T, const uint8_t* exclude, int hit, int miss,
+                           int lmin, int lmax, int threshold)
+{
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    uint8_t* is_hit = (uint8_t*)calloc((size_t)nvox, 1);
+    uint8_t* is_free = (uint8_t*)calloc((size_t)nvox, 1);
+    const int n3[3] = {nx, ny, nz};
+    /* sensor position in voxel units: the translation column of T */
+    float a[3];
+    for (int i = 0; i < 3; ++i) a[i] = (T[4 * i + 3] - origin[i]) / voxel;
+    for (int64_t k = 0; k < n; ++k) {
+        const float* p = pts + 3 * k;
+        float m[3], b[3];
+        int e[3], ok = 1;
+        for (int i = 0; i < 3; ++i) {
+            m[i] = xform_row(T, i, p[0], p[1], p[2]);
+            b[i] = (m[i] - origin[i]) / voxel;
+            if (!(b[i] >= 0.0f && b[i] < (float)n3[i])) ok = 0;  /* drops NaN */
+        }
+        if (!ok) continue;
+        for (int i = 0; i < 3; ++i) e[i] = (int)floorf(b[i]);
+        const int64_t le = lin3(e[0], e[1], e[2], nx, ny);
+        if (exclude && exclude[le]) continue;
+        is_hit[le] = 1;
+        /* the walk's voxels before the endpoint are crossed: free */
+        int cur[3], end[3], step[3], left[3], total = 0;
+        float tmax[3], tdel[3];
+        for (int i = 0; i < 3; ++i) {
+            cur[i] = (int)floorf(a[i]);
+            end[i] = e[i];
+            const float d = b[i] - a[i];
+            step[i] = end[i] > cur[i] ? 1 : (end[i] < cur[i] ? -1 : 0);
+            left[i] = step[i] > 0 ? end[i] - cur[i] : cur[i] - end[i];
+            total += left[i];
+            if (step[i] != 0) {
+                const float bound = (float)(step[i] > 0 ? cur[i] + 1 : cur[i]);
+                tmax[i] = (bound - a[i]) / d;
+                tdel[i] = 1.0f / fabsf(d);
+            } else {
+                tmax[i] = INFINITY;
+                tdel[i] = 0.0f;
+            }
+        }
+        for (int s = 0; s < total; ++s) {
+            if (cur[0] >= 0 && cur[0] < nx && cur[1] >= 0 && cur[1] < ny && cur[2] >= 0 && cur[2] < nz)
+                is_free[lin3(cur[0], cur[1], cur[2], nx, ny)] = 1;
+            int ax = -1;
+            for (int i = 0; i < 3; ++i)
+                if (left[i] > 0 && (ax < 0 || tmax[i] < tmax[ax])) ax = i;
+            cur[ax] += step[ax];
+            left[ax] -= 1;
+            tmax[ax] = tmax[ax] + tdel[ax];
+        }
+    }
+    for (int64_t v = 0; v < nvox; ++v) {
+        int l = logodds[v];
+        if (is_hit[v]) {
+            l += hit;
+            if (l > lmax) l = lmax;
+        } else if (is_free[v]) {
+            l += miss;
+            if (l < lmin) l = lmin;
+        }
+        logodds[v] = (int16_t)l;
+        occ[v] = l > threshold ? 1 : 0;
+    }
+    free(is_hit);
+    free(is_free);
+}

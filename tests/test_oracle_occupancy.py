@@ -1,0 +1,144 @@
+"""Pins of the CPU oracle's probabilistic occupancy update (Sec. III-A: each
+point's voxel is updated as a Bayesian process) and of the ray walk it uses
+for the voxels a sensor ray crosses.  The walk is checked against the
+geometry (which boxes a segment passes through, in float64), the update
+against worked examples and against plain insertion."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_02363_amd import inputs
+
+
+def crossed_boxes(a, b):
+    """Voxels whose box the open segment a-b passes through with positive
+    length (float64 slab test), with the parameter intervals."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    lo = np.floor(np.minimum(a, b)).astype(int)
+    hi = np.floor(np.maximum(a, b)).astype(int)
+    out = set()
+    d = b - a
+    for x in range(lo[0], hi[0] + 1):
+        for y in range(lo[1], hi[1] + 1):
+            for z in range(lo[2], hi[2] + 1):
+                t0, t1 = 0.0, 1.0
+                for i, c in enumerate((x, y, z)):
+                    if d[i] == 0:
+                        if not (c <= a[i] < c + 1):
+                            t0, t1 = 1.0, 0.0
+                        continue
+                    u0, u1 = (c - a[i]) / d[i], (c + 1 - a[i]) / d[i]
+                    t0, t1 = max(t0, min(u0, u1)), min(t1, max(u0, u1))
+                if t1 - t0 > 1e-12:
+                    out.add((x, y, z))
+    return out
+
+
+def near_tie(a, b, tol=1e-4):
+    """True if two boundary crossings of different axes (or a crossing and
+    an endpoint) fall within tol of each other along the segment."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    d = b - a
+    ts = [0.0, 1.0]
+    for i in range(3):
+        if d[i] == 0:
+            continue
+        lo, hi = sorted((a[i], b[i]))
+        for c in range(int(np.floor(lo)) + 1, int(np.floor(hi)) + 1):
+            ts.append((c - a[i]) / d[i])
+    ts.sort()
+    return any(t1 - t0 < tol for t0, t1 in zip(ts, ts[1:]))
+
+
+def test_ray_walk_matches_geometry():
+    g = inputs.rng(40)
+    checked = 0
+    for _ in range(400):
+        a = g.uniform(0, 12, 3).astype(np.float32)
+        b = g.uniform(0, 12, 3).astype(np.float32)
+        if near_tie(a, b):
+            continue
+        w = oracle.ray_walk(a, b)
+        # one axis step at a time, from floor(a) to floor(b)
+        assert tuple(w[0]) == tuple(np.floor(a).astype(int))
+        assert tuple(w[-1]) == tuple(np.floor(b).astype(int))
+        assert (np.abs(np.diff(w, axis=0)).sum(axis=1) == 1).all()
+        assert set(map(tuple, w)) == crossed_boxes(a, b)
+        checked += 1
+    assert checked > 300
+
+
+def test_ray_walk_axis_aligned_and_single_voxel():
+    assert oracle.ray_walk([2.5, 3.5, 1.5], [2.7, 3.2, 1.9]).tolist() == [[2, 3, 1]]
+    w = oracle.ray_walk([0.5, 0.5, 0.5], [0.5, 0.5, 5.5])
+    assert w.tolist() == [[0, 0, z] for z in range(6)]
+    w = oracle.ray_walk([5.5, 0.5, 0.5], [0.5, 0.5, 0.5])
+    assert w.tolist() == [[x, 0, 0] for x in range(5, -1, -1)]
+
+
+def line_grid(n=8):
+    return inputs.Grid(n, 1, 1, (0.0, 0.0, 0.0), 0.1)
+
+
+def T_at(x, y, z):
+    """Sensor pose: identity rotation at (x, y, z) metres."""
+    return np.array([1, 0, 0, x, 0, 1, 0, y, 0, 0, 1, z], np.float32)
+
+
+def test_update_by_hand_on_a_line():
+    g = line_grid()
+    L = np.zeros(g.n, np.int16)
+    occ = np.zeros(g.n, np.uint8)
+    T = T_at(0.05, 0.05, 0.05)                   # sensor at the centre of voxel 0
+    pts = np.array([[0.5, 0.0, 0.0]], np.float32)  # endpoint: centre of voxel 5
+    oracle.update_logodds(g, L, occ, pts, T)
+    assert L.tolist() == [-41] * 5 + [85, 0, 0]
+    assert occ.tolist() == [0] * 5 + [1, 0, 0]
+    for _ in range(10):
+        oracle.update_logodds(g, L, occ, pts, T)
+    # clamped at the bounds
+    assert L.tolist() == [-200] * 5 + [350, 0, 0]
+    # two points on one ray: the nearer voxel is a hit although the farther
+    # point's ray crosses it; points in one voxel count once per frame
+    L[:] = 0
+    pts2 = np.array([[0.3, 0.0, 0.0], [0.5, 0.0, 0.0], [0.52, 0.01, 0.0]], np.float32)
+    oracle.update_logodds(g, L, occ, pts2, T)
+    assert L.tolist() == [-41, -41, -41, 85, -41, 85, 0, 0]
+
+
+def test_update_exclusion_and_outside_points():
+    g = line_grid()
+    L = np.zeros(g.n, np.int16)
+    occ = np.zeros(g.n, np.uint8)
+    ex = np.zeros(g.n, np.uint8)
+    ex[5] = 1
+    pts = np.array([[0.5, 0.0, 0.0], [1.5, 0.0, 0.0], [np.nan, 0, 0]], np.float32)
+    oracle.update_logodds(g, L, occ, pts, T_at(0.05, 0.05, 0.05), exclude=ex)
+    assert (L == 0).all() and (occ == 0).all()
+    # a sensor outside the map: only the crossed voxels inside are updated
+    oracle.update_logodds(g, L, occ, np.array([[0.6, 0, 0]], np.float32), T_at(-0.35, 0.05, 0.05))
+    assert L.tolist() == [-41, -41, 85, 0, 0, 0, 0, 0]
+
+
+def test_hits_alone_equal_plain_insertion():
+    """With no miss update, one frame on a fresh grid occupies exactly the
+    voxels plain insertion sets (same transform and discretization)."""
+    ci = inputs.cycle_inputs(3, n_frames=1, grid=inputs.Grid(48, 40, 32, (0.9, 0.8, 0.0), 0.04))
+    g = ci.grid
+    ex = np.zeros(g.shape, np.uint8)
+    oracle.insert_links(g, ex, ci.link_pts, ci.link_off, ci.robot.poses12(ci.joint_states[0]), 0xFF)
+    ref = np.zeros(g.shape, np.uint8)
+    oracle.insert_points(g, ref, ci.frames[0], ci.T_map_cam, exclude=ex)
+    L = np.zeros(g.n, np.int16)
+    occ = np.zeros(g.n, np.uint8)
+    oracle.update_logodds(g, L, occ, ci.frames[0], ci.T_map_cam, exclude=ex, miss=0)
+    assert ref.sum() > 100
+    assert np.array_equal(occ.reshape(g.shape), ref)
+    # with misses, the crossed voxels lose evidence and hits still win
+    L2 = np.zeros(g.n, np.int16)
+    occ2 = np.zeros(g.n, np.uint8)
+    oracle.update_logodds(g, L2, occ2, ci.frames[0], ci.T_map_cam, exclude=ex)
+    assert np.array_equal(occ2.reshape(g.shape), ref)
+    assert (L2 < 0).sum() > ref.sum() and set(np.unique(L2)) <= {-41, 0, 85}
