@@ -429,6 +429,10 @@ void oracle_update_logodds(int nx, int ny, int nz, const float* origin, float vo
         const int64_t le = lin3(e[0], e[1], e[2], nx, ny);
         if (exclude && exclude[le]) continue;
         is_hit[le] = 1;
+        /* a sensor farther than 2^16 voxels on an axis (or not finite)
+         * walks no crossings */
+        if (!(fabsf(a[0]) <= 65536.0f && fabsf(a[1]) <= 65536.0f && fabsf(a[2]) <= 65536.0f))
+            continue;
         /* the walk's voxels before the endpoint are crossed: free */
         int cur[3], end[3], step[3], left[3], total = 0;
         float tmax[3], tdel[3];

@@ -142,3 +142,21 @@ def test_hits_alone_equal_plain_insertion():
     oracle.update_logodds(g, L2, occ2, ci.frames[0], ci.T_map_cam, exclude=ex)
     assert np.array_equal(occ2.reshape(g.shape), ref)
     assert (L2 < 0).sum() > ref.sum() and set(np.unique(L2)) <= {-41, 0, 85}
+
+
+def test_far_sensor_walks_no_crossings():
+    """A sensor beyond 2^16 voxels on an axis (or with a NaN position) only
+    adds its hits; one just inside that bound walks its whole ray."""
+    g = line_grid()
+    L = np.zeros(g.n, np.int16)
+    occ = np.zeros(g.n, np.uint8)
+    far = T_at(-7000.0, 0.05, 0.05)            # 70000 voxels of 0.1 m away
+    oracle.update_logodds(g, L, occ, np.array([[7000.25, 0, 0]], np.float32), far)
+    assert L.tolist() == [0, 0, 85, 0, 0, 0, 0, 0]
+    L[:] = 0
+    oracle.update_logodds(g, L, occ, np.array([[0.25, 0, 0]], np.float32), T_at(np.nan, 0.05, 0.05))
+    assert (L == 0).all()   # the NaN pose also makes the endpoint NaN: nothing
+    L[:] = 0
+    near = T_at(-6000.0, 0.05, 0.05)           # 60000 voxels: within the bound
+    oracle.update_logodds(g, L, occ, np.array([[6000.45, 0, 0]], np.float32), near)
+    assert L.tolist() == [-41] * 4 + [85, 0, 0, 0]
