@@ -102,6 +102,52 @@ int edt_insert_points(const edt_grid_t* grid, uint8_t* occ, const float* pts, in
                       const float* T_map_sensor, const uint8_t* exclude, void* stream);
 
 /*
+ * Probabilistic occupancy (Sec. III-A: the occupancy of each point's voxel is
+ * updated as a Bayesian process).  A persistent int16 log-odds grid (same
+ * layout as occ) is updated once per frame:
+ *   - a voxel holding at least one endpoint gets one hit update,
+ *     L = min(L + hit, max);
+ *   - a voxel that some sensor ray crosses on its way to an endpoint, and
+ *     that holds no endpoint, gets one miss update, L = max(L + miss, min);
+ *   - occ = 1 iff L > threshold (0 otherwise), ready for edt_compute.
+ * Only points whose endpoint voxel lies in the map and is not set in
+ * exclude take part (exclusion as in edt_insert_points).  The ray is walked
+ * voxel by voxel from the sensor's voxel (the translation of T_map_sensor)
+ * to the endpoint's: each step crosses the boundary with the smallest ray
+ * parameter among the axes that still have voxels to cross (x before y
+ * before z on ties), in float32 with one rounding per operation, so the
+ * walk ends exactly on the endpoint voxel.  Voxels outside the map are
+ * skipped; a sensor farther than 65536 voxels from the map origin on some
+ * axis (or with a non-finite position) walks no crossings, its hits still
+ * count.  Units: hundredths of a nat in the defaults below.
+ */
+typedef struct edt_logodds_t {
+    int16_t hit;         /* added for an endpoint, e.g. 85 = ln(0.7 / 0.3) */
+    int16_t miss;        /* added for a crossing, e.g. -41 = ln(0.4 / 0.6) */
+    int16_t min, max;    /* clamp, e.g. -200 and 350 */
+    int16_t threshold;   /* occupied iff log-odds > threshold, e.g. 0 */
+    int16_t reserved;
+} edt_logodds_t;
+
+/* Workspace of the per-frame hit and crossing flags: 2 bytes per voxel.
+ * Must be zero before the first update (edt_logodds_reset); every update
+ * leaves it zero again. */
+size_t edt_logodds_workspace_bytes(const edt_grid_t* grid);
+
+/* log-odds = 0 (probability one half) everywhere and the workspace zeroed;
+ * fill kernels only (graph-capturable). */
+int edt_logodds_reset(const edt_grid_t* grid, int16_t* logodds, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* One frame: pts float32 [n][3] in the sensor frame, T_map_sensor device
+ * float32 [12] (row-major 3x4), exclude nullable; logodds updated in place,
+ * occ fully overwritten.  Errors: EDT_ERR_ARG (bad pointers, min > max),
+ * EDT_ERR_WORKSPACE. */
+int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, const float* pts,
+                       int64_t n, const float* T_map_sensor, const uint8_t* exclude,
+                       const edt_logodds_t* params, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * edt_insert_links -- insert the robot's voxelized links placed by joint
  * state (Sec. III-A: offline link voxel models inserted according to the
  * joint state; Alg. 2 UpdateLinks/Insert; self-collision set O_L of

@@ -71,6 +71,106 @@ __global__ void k_insert_points(GridArgs g, const float* __restrict__ pts, int64
     insert_point(g, t, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], occ, exclude);
 }
 
+// Probabilistic occupancy (Sec. III-A).  One thread per point: the
+// endpoint's voxel is flagged as a hit and every voxel the sensor ray
+// crosses before it as free, for this frame.  The walk goes voxel by voxel
+// from the sensor's voxel (Amanatides-Woo order): each step crosses the
+// boundary with the smallest parameter tmax among the axes that still have
+// voxels to cross, x before y before z on ties, so it ends exactly on the
+// endpoint voxel.  float32, one rounding per operation, no contraction.
+__global__ void k_logodds_rays(GridArgs g, const float* __restrict__ pts, int64_t n,
+                               const float* __restrict__ T, const uint8_t* __restrict__ exclude,
+                               uint8_t* __restrict__ hit, uint8_t* __restrict__ fre)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float t[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) t[k] = T[k];
+    const float px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
+    const float o[3] = {g.ox, g.oy, g.oz};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    float b[3];
+    int e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float m = xform_row(t, k, px, py, pz);
+        b[k] = (m - o[k]) / g.v;
+        if (!(b[k] >= 0.0f && b[k] < (float)nn[k])) return;   // also drops NaN
+        e[k] = (int)floorf(b[k]);
+    }
+    const int64_t le = e[0] + (int64_t)g.nx * (e[1] + (int64_t)g.ny * e[2]);
+    if (exclude && exclude[le]) return;
+    hit[le] = 1;
+    int cur[3], step[3], left[3], total = 0;
+    float tmax[3], tdel[3];
+    float a[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a[k] = (t[4 * k + 3] - o[k]) / g.v;   // sensor position, voxel units
+        // a sensor farther than 2^16 voxels on an axis, or not finite:
+        // no crossings are walked (its hits still count)
+        if (!(fabsf(a[k]) <= 65536.0f)) return;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        cur[k] = (int)floorf(a[k]);
+        const float d = b[k] - a[k];
+        step[k] = e[k] > cur[k] ? 1 : (e[k] < cur[k] ? -1 : 0);
+        left[k] = step[k] > 0 ? e[k] - cur[k] : cur[k] - e[k];
+        total += left[k];
+        if (step[k] != 0) {
+            const float bound = (float)(step[k] > 0 ? cur[k] + 1 : cur[k]);
+            tmax[k] = (bound - a[k]) / d;
+            tdel[k] = 1.0f / fabsf(d);
+        } else {
+            tmax[k] = __builtin_huge_valf();
+            tdel[k] = 0.0f;
+        }
+    }
+    for (int s = 0; s < total; ++s) {
+        if ((unsigned)cur[0] < (unsigned)g.nx && (unsigned)cur[1] < (unsigned)g.ny &&
+            (unsigned)cur[2] < (unsigned)g.nz)
+            fre[cur[0] + (int64_t)g.nx * (cur[1] + (int64_t)g.ny * cur[2])] = 1;
+        int ax = left[0] > 0 ? 0 : -1;
+        if (left[1] > 0 && (ax < 0 || tmax[1] < tmax[ax])) ax = 1;
+        if (left[2] > 0 && (ax < 0 || tmax[2] < tmax[ax])) ax = 2;
+        // one of the axes has voxels left while s < total
+        cur[ax] += step[ax];
+        left[ax] -= 1;
+        tmax[ax] = tmax[ax] + tdel[ax];
+    }
+}
+
+struct LogOdds {
+    int hit, miss, lmin, lmax, threshold;
+};
+
+// One thread per 4 voxels: hit beats free, clamp, threshold, and clear the
+// frame's flags for the next frame.
+__global__ void k_logodds_update(int64_t n, LogOdds p, int16_t* __restrict__ L,
+                                 uint8_t* __restrict__ occ, uint8_t* __restrict__ hit,
+                                 uint8_t* __restrict__ fre)
+{
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t v = i0 + k;
+        if (v >= n) return;
+        int l = L[v];
+        if (hit[v]) {
+            l = min(l + p.hit, p.lmax);
+            hit[v] = 0;
+            fre[v] = 0;
+        } else if (fre[v]) {
+            l = max(l + p.miss, p.lmin);
+            fre[v] = 0;
+        }
+        L[v] = (int16_t)l;
+        occ[v] = l > p.threshold ? 1 : 0;
+    }
+}
+
 constexpr int MAX_LINKS = 64;
 struct LinkSegs {
     int n;                       // segments (selected links)
@@ -274,6 +374,86 @@ int edt_insert_points(const edt_grid_t* grid, uint8_t* occ, const float* pts, in
     hipLaunchKernelGGL(k_insert_points, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream),
                        grid_args(grid), pts, n, T, exclude, occ);
     return check_launch("k_insert_points");
+}
+
+size_t edt_logodds_workspace_bytes(const edt_grid_t* grid)
+{
+    if (check_grid(grid)) return 0;
+    return (size_t)(2 * grid_voxels(grid) + 255) / 256 * 256;
+}
+
+namespace {
+int fill_zero(void* p, int64_t bytes, hipStream_t st)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    int64_t head = (int64_t)((16 - (a & 15)) & 15);
+    if (head > bytes) head = bytes;
+    const int64_t body = (bytes - head) / 16, tail = bytes - head - 16 * body;
+    const int64_t work = std::max(std::max(body, head), tail);
+    if (work == 0) return EDT_OK;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st,
+                       static_cast<uint8_t*>(p), head, body, tail);
+    return check_launch("k_fill_zero");
+}
+}  // namespace
+
+int edt_logodds_reset(const edt_grid_t* grid, int16_t* logodds, void* ws, size_t ws_bytes,
+                      void* stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!logodds || !ws) {
+        set_error("edt_logodds_reset: NULL log-odds or workspace");
+        return EDT_ERR_ARG;
+    }
+    if (ws_bytes < edt_logodds_workspace_bytes(grid)) {
+        set_error("edt_logodds_reset: workspace of %zu bytes is below %zu", ws_bytes,
+                  edt_logodds_workspace_bytes(grid));
+        return EDT_ERR_WORKSPACE;
+    }
+    const hipStream_t st = as_stream(stream);
+    rc = fill_zero(logodds, 2 * grid_voxels(grid), st);
+    if (!rc) rc = fill_zero(ws, 2 * grid_voxels(grid), st);
+    return rc;
+}
+
+int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, const float* pts,
+                       int64_t n, const float* T, const uint8_t* exclude, const edt_logodds_t* params,
+                       void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!logodds || !occ || !params || !ws || n < 0 || (n > 0 && (!pts || !T))) {
+        set_error("edt_update_logodds: bad pointer or negative count");
+        return EDT_ERR_ARG;
+    }
+    if (params->min > params->max) {
+        set_error("edt_update_logodds: clamp range [%d, %d] is empty", params->min, params->max);
+        return EDT_ERR_ARG;
+    }
+    if (ws_bytes < edt_logodds_workspace_bytes(grid)) {
+        set_error("edt_update_logodds: workspace of %zu bytes is below %zu", ws_bytes,
+                  edt_logodds_workspace_bytes(grid));
+        return EDT_ERR_WORKSPACE;
+    }
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > INT_MAX) {
+        set_error("edt_update_logodds: too many points");
+        return EDT_ERR_ARG;
+    }
+    const hipStream_t st = as_stream(stream);
+    const int64_t nv = grid_voxels(grid);
+    uint8_t* hit = static_cast<uint8_t*>(ws);
+    uint8_t* fre = hit + nv;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_logodds_rays, dim3((unsigned)blocks), dim3(256), 0, st, grid_args(grid),
+                           pts, n, T, exclude, hit, fre);
+        if ((rc = check_launch("k_logodds_rays"))) return rc;
+    }
+    const LogOdds p{params->hit, params->miss, params->min, params->max, params->threshold};
+    hipLaunchKernelGGL(k_logodds_update, dim3((unsigned)((nv + 1023) / 1024)), dim3(256), 0, st, nv, p,
+                       logodds, occ, hit, fre);
+    return check_launch("k_logodds_update");
 }
 
 int edt_insert_links(const edt_grid_t* grid, uint8_t* occ, const float* link_pts,

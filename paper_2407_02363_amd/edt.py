@@ -44,6 +44,15 @@ class Tuning(ctypes.Structure):
     _fields_ = [("xy_tile", ctypes.c_int32), ("z_tile", ctypes.c_int32), ("z_group", ctypes.c_int32)]
 
 
+class LogOdds(ctypes.Structure):
+    _fields_ = [("hit", ctypes.c_int16), ("miss", ctypes.c_int16), ("min", ctypes.c_int16),
+                ("max", ctypes.c_int16), ("threshold", ctypes.c_int16), ("reserved", ctypes.c_int16)]
+
+
+# hundredths of a nat: P(hit) 0.7, P(miss) 0.4, clamp [-2.0, 3.5], occupied above 0
+LOGODDS_DEFAULT = (85, -41, -200, 350, 0)
+
+
 class BatchMap(ctypes.Structure):
     _fields_ = [("grid", EdtGrid), ("occ", ctypes.c_void_p), ("d2", ctypes.c_void_p),
                 ("site", ctypes.c_void_p)]
@@ -56,7 +65,8 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_insert_points", "edt_insert_links", "edt_workspace_bytes", "edt_compute",
             "edt_query_spheres", "edt_compute_stage", "edt_default_tuning", "edt_compute_tuned",
             "edt_autotune", "edt_batch_workspace_bytes", "edt_compute_batched", "edt_batch_status",
-            "edt_compute_many",
+            "edt_compute_many", "edt_logodds_workspace_bytes", "edt_logodds_reset",
+            "edt_update_logodds",
             "edt_autotune_batched"]
 
 BATCH_MAX = 48
@@ -93,6 +103,10 @@ def lib():
         "edt_batch_workspace_bytes": ([i32], ctypes.c_size_t),
         "edt_compute_batched": ([P, i32, P, ctypes.c_size_t, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_compute_many": ([P, i32, ctypes.POINTER(Tuning), P], ctypes.c_int),
+        "edt_logodds_workspace_bytes": ([G], ctypes.c_size_t),
+        "edt_logodds_reset": ([G, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "edt_update_logodds": ([G, P, P, P, i64, P, P, ctypes.POINTER(LogOdds), P, ctypes.c_size_t, P],
+                               ctypes.c_int),
         "edt_batch_status": ([P, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
         "edt_autotune_batched": ([P, i32, P, ctypes.c_size_t, i32, ctypes.POINTER(Tuning),
                                   ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
@@ -309,3 +323,33 @@ def edt_autotune_batched(maps, ws, reps: int = 5, stream=None):
                                       ctypes.byref(t), ctypes.byref(us), _stream(stream)),
            "edt_autotune_batched")
     return (t.xy_tile, t.z_tile), float(us.value)
+
+
+def edt_logodds_workspace_bytes(grid) -> int:
+    return int(lib().edt_logodds_workspace_bytes(ctypes.byref(make_grid(grid))))
+
+
+def new_logodds_workspace(grid, device="cuda"):
+    return torch.zeros(edt_logodds_workspace_bytes(grid), dtype=torch.uint8, device=device)
+
+
+def edt_logodds_reset(grid, logodds, ws, stream=None):
+    g = make_grid(grid)
+    _check(lib().edt_logodds_reset(ctypes.byref(g), _dev(logodds, torch.int16, "logodds", _n(g)),
+                                   _dev(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)),
+           "edt_logodds_reset")
+
+
+def edt_update_logodds(grid, logodds, occ, pts, T_map_sensor, ws, exclude=None,
+                       params=LOGODDS_DEFAULT, stream=None):
+    """params: (hit, miss, min, max, threshold) in the log-odds units."""
+    g = make_grid(grid)
+    n = pts.shape[0] if pts.dim() == 2 else pts.numel() // 3
+    p = LogOdds(*[int(x) for x in params], 0)
+    _check(lib().edt_update_logodds(ctypes.byref(g), _dev(logodds, torch.int16, "logodds", _n(g)),
+                                    _dev(occ, torch.uint8, "occ", _n(g)),
+                                    _dev(pts, torch.float32, "pts", 3 * n), n,
+                                    _dev(T_map_sensor, torch.float32, "T_map_sensor", 12),
+                                    _dev(exclude, torch.uint8, "exclude", _n(g)), ctypes.byref(p),
+                                    _dev(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)),
+           "edt_update_logodds")

@@ -97,6 +97,18 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), 2, ctypes.byref(bad_t), None) == -5
     maps[1].d2 = None
     assert lib.edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), 2, ctypes.byref(bad_t), None) == -1
+    # log-odds update: workspace size, clamp range and NULLs, before any launch
+    assert lib.edt_logodds_workspace_bytes(ctypes.byref(ok)) >= 2 * ok.nx * ok.ny * ok.nz
+    lo = edt.LogOdds(85, -41, 10, -10, 0, 0)
+    wsb = lib.edt_logodds_workspace_bytes(ctypes.byref(ok))
+    assert lib.edt_update_logodds(ctypes.byref(ok), one, one, one, 1, one, None, ctypes.byref(lo),
+                                  one, wsb, None) == -1
+    lo = edt.LogOdds(*edt.LOGODDS_DEFAULT, 0)
+    assert lib.edt_update_logodds(ctypes.byref(ok), one, one, one, 1, one, None, ctypes.byref(lo),
+                                  one, wsb - 1, None) == -3
+    assert lib.edt_update_logodds(ctypes.byref(ok), one, None, one, 1, one, None, ctypes.byref(lo),
+                                  one, wsb, None) == -1
+    assert lib.edt_logodds_reset(ctypes.byref(ok), one, one, 16, None) == -3
     huge = edt.EdtGrid(8, 1024, 8, (ctypes.c_float * 3)(0, 0, 0), 0.01)
     assert lib.edt_compute_tuned(ctypes.byref(huge), one, one, one,
                                  ctypes.byref(edt.Tuning(64, 8)), None) == -5
