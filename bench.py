@@ -220,6 +220,64 @@ def batched_workload(args, torch, edt, inputs, host_latency=True):
     return res
 
 
+def occupancy_workload(args, torch, edt, ci, cyc):
+    """Probabilistic occupancy front end on the control-cycle map: the
+    per-frame log-odds update alone (ray walks + voxel update), and the cycle
+    with the environment map built from the persistent log-odds grid instead
+    of plain insertion."""
+    g = ci.grid
+    dev = cyc.dev
+    L = torch.zeros(g.n, dtype=torch.int16, device=dev)
+    occ = torch.zeros(g.n, dtype=torch.uint8, device=dev)
+    ws = edt.new_logodds_workspace(g, dev)
+    edt.edt_logodds_reset(g, L, ws)
+    frames = cyc.frames
+    nf = frames.shape[0]
+
+    def update(k):
+        edt.edt_update_logodds(g, L, occ, frames[k % nf], cyc.T, ws, exclude=cyc.occ_self)
+
+    for k in range(5):
+        update(k)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    reps = max(50, args.steps // 4)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for k in range(reps):
+        update(k)
+    b.record(st)
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+
+    def cycle(k):
+        s = k % cyc.n_states
+        edt.edt_clear(g, cyc.occ_self)
+        edt.edt_insert_links(g, cyc.occ_self, cyc.link_pts, cyc.link_off, cyc.poses[s], cyc.self_mask)
+        update(k)
+        edt.edt_compute_many(edt.batch_maps([g, g], [occ, cyc.occ_self], [cyc.d2_env, cyc.d2_self],
+                                            [cyc.site_env, cyc.site_self]))
+        edt.edt_query_spheres(g, cyc.d2_env, cyc.site_env, cyc.centres[s], cyc.radii, cyc.out_env)
+        edt.edt_query_spheres(g, cyc.d2_self, cyc.site_self, cyc.centres[s], cyc.radii, cyc.out_self)
+
+    for k in range(5):
+        cycle(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        cycle(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"workload": "256x256x128 map at 1 cm, persistent int16 log-odds, one 307200-point frame "
+                        "per update (hit 85, miss -41, clamp [-200, 350] hundredths of a nat), "
+                        "robot voxels excluded, every ray walked from the camera",
+            "update_ms": ms, "points_per_s": frames.shape[1] / (ms * 1e-3),
+            "cycle_eager_ms": 1e3 * el / args.steps,
+            "cycle_mvox_s": 2 * g.n * args.steps / el / 1e6,
+            "occupied_voxels": int(occ.sum().item())}
+
+
 def surrogate_workload(args, torch, inputs):
     """Learned self-distance surrogate on the 128^3 self-map: exact-EDT
     labels, GPU training, worst held-out error, and look-ahead evaluation
@@ -515,6 +573,9 @@ def main():
     edt_only = {"avg_us": 1e3 * t_all, "mvox_s": nvox / (t_all * 1e-3) / 1e6,
                 "algorithmic_GBs_9B": edt_alg, "frac_9B": edt_alg / HBM_PEAK_GBS}
 
+    log("[bench] probabilistic occupancy front end")
+    occupancy = occupancy_workload(args, torch, edt, ci, cyc)
+
     batched = None
     if args.batch_maps > 0:
         batched = batched_workload(args, torch, edt, inputs, host_latency=True)
@@ -535,7 +596,7 @@ def main():
                       "points_per_frame": int(ci.frames[0].shape[0]),
                       "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
            "timing": mode, "eager": eager, "latency": latency,
-           "cycle_variants": variants, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
+           "cycle_variants": variants, "occupancy": occupancy, "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
            "batched": batched, "surrogate": surrogate,
            "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",
                              "workload": "live camera scene, 256x256x128 at 1 cm"}}

@@ -12,6 +12,7 @@ Functions (each cites the paper passage it follows in its docstring):
   query_spheres(...)    closest obstacle at sphere centres (Alg. 2, Eq. dist)
   update_logodds(...)   per-frame Bayesian occupancy update (Sec. III-A)
   ray_walk(a, b)        voxels a sensor ray crosses (the update's traversal)
+  outlier_filter(...)   statistical outlier filtering of a cloud (Sec. III-A)
 """
 from __future__ import annotations
 
@@ -65,6 +66,9 @@ def _load():
         lib.oracle_update_logodds.argtypes = ([ctypes.c_int] * 3 + [P, ctypes.c_float, P, P, P,
                                               ctypes.c_int64, P, P] + [ctypes.c_int] * 5)
         lib.oracle_update_logodds.restype = None
+        lib.oracle_outlier_filter.argtypes = [P, ctypes.c_int64, ctypes.c_int, ctypes.c_float,
+                                              ctypes.c_double, P, P, P]
+        lib.oracle_outlier_filter.restype = None
         _lib = lib
     return _lib
 
@@ -175,3 +179,18 @@ def update_logodds(grid, logodds: np.ndarray, occ: np.ndarray, pts: np.ndarray, 
                                   pts.shape[0], _ptr(T), None if ex is None else _ptr(ex),
                                   int(hit), int(miss), int(lmin), int(lmax), int(threshold))
     return logodds, occ
+
+
+def outlier_filter(pts: np.ndarray, k: int = 8, radius: float = 0.01, alpha: float = 1.0):
+    """Statistical outlier filtering (Sec. III-A): (keep uint8 [n], mean
+    neighbour distance float32 [n] (NaN for non-finite points), (mu, sigma,
+    threshold)).  Brute force over all pairs: O(n^2)."""
+    pts = np.ascontiguousarray(pts, np.float32).reshape(-1, 3)
+    n = pts.shape[0]
+    assert 1 <= k <= 64
+    keep = np.zeros(n, np.uint8)
+    dm = np.zeros(n, np.float32)
+    stats = np.zeros(3, np.float64)
+    _load().oracle_outlier_filter(_ptr(pts), n, int(k), float(radius), float(alpha), _ptr(keep),
+                                  _ptr(dm), _ptr(stats))
+    return keep, dm, tuple(float(x) for x in stats)

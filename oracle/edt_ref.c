@@ -478,3 +478,78 @@ void oracle_update_logodds(int nx, int ny, int nz, const float* origin, float vo
     free(is_hit);
     free(is_free);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Statistical outlier filtering of the raw cloud (Sec. III-A: points are   */
+/* filtered by their Euclidean distance to their neighbours).  For every    */
+/* finite point i:                                                          */
+/*   s_ij = (dx*dx + dy*dy) + dz*dz of the float32 differences p_j - p_i;  */
+/*   its neighbours are the other points with s_ij <= R*R, of which the k   */
+/*   with the smallest s_ij count (fewer if there are fewer);               */
+/*   d_i = (sum of sqrtf(s_ij) over them in ascending order + (k - m) * R)  */
+/*         / k, m = number counted: a missing neighbour counts as R.        */
+/* Over the finite points, mu and the sample standard deviation sigma of    */
+/* d_i come from exact fixed-point sums (d_i in units of 2^-40, d_i^2 in    */
+/* units of 2^-48); point i is kept iff it is finite and d_i <= mu +        */
+/* alpha * sigma (double).  float32 with one rounding per operation for d_i.*/
+/* ------------------------------------------------------------------------ */
+static int finite3(const float* p)
+{
+    return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
+}
+
+void oracle_outlier_filter(const float* pts, int64_t n, int k, float R, double alpha,
+                           uint8_t* keep, float* dmean, double* stats)
+{
+    const float rr = R * R;
+    int64_t S1 = 0, S2 = 0, cnt = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : S1, S2, cnt)
+    for (int64_t i = 0; i < n; ++i) {
+        const float* p = pts + 3 * i;
+        if (!finite3(p)) {
+            dmean[i] = NAN;
+            continue;
+        }
+        float best[64];
+        int m = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const float* q = pts + 3 * j;
+            if (!finite3(q)) continue;
+            const float dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
+            const float s = (dx * dx + dy * dy) + dz * dz;
+            if (!(s <= rr)) continue;
+            /* keep the k smallest, sorted ascending */
+            if (m < k) {
+                int t = m++;
+                while (t > 0 && best[t - 1] > s) { best[t] = best[t - 1]; --t; }
+                best[t] = s;
+            } else if (s < best[k - 1]) {
+                int t = k - 1;
+                while (t > 0 && best[t - 1] > s) { best[t] = best[t - 1]; --t; }
+                best[t] = s;
+            }
+        }
+        float acc = 0.0f;
+        for (int t = 0; t < m; ++t) acc = acc + sqrtf(best[t]);
+        acc = acc + (float)(k - m) * R;
+        const float d = acc / (float)k;
+        dmean[i] = d;
+        const double dd = (double)d;
+        S1 += (int64_t)rint(dd * 1099511627776.0);             /* 2^40 */
+        S2 += (int64_t)rint(dd * dd * 281474976710656.0);      /* 2^48 */
+        cnt += 1;
+    }
+    double mu = 0.0, sigma = 0.0;
+    if (cnt > 0) mu = (double)S1 / 1099511627776.0 / (double)cnt;
+    if (cnt > 1) {
+        const double var = ((double)S2 / 281474976710656.0 - (double)cnt * mu * mu) / (double)(cnt - 1);
+        sigma = var > 0.0 ? sqrt(var) : 0.0;
+    }
+    const double thr = mu + alpha * sigma;
+    for (int64_t i = 0; i < n; ++i)
+        keep[i] = finite3(pts + 3 * i) && (double)dmean[i] <= thr ? 1 : 0;
+    stats[0] = mu;
+    stats[1] = sigma;
+    stats[2] = thr;
+}
