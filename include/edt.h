@@ -140,12 +140,45 @@ int edt_logodds_reset(const edt_grid_t* grid, int16_t* logodds, void* ws, size_t
                       void* stream);
 
 /* One frame: pts float32 [n][3] in the sensor frame, T_map_sensor device
- * float32 [12] (row-major 3x4), exclude nullable; logodds updated in place,
- * occ fully overwritten.  Errors: EDT_ERR_ARG (bad pointers, min > max),
- * EDT_ERR_WORKSPACE. */
+ * float32 [12] (row-major 3x4), keep nullable uint8 [n] (0 = point filtered
+ * out, e.g. by edt_outlier_filter), exclude nullable; logodds updated in
+ * place, occ fully overwritten.  Errors: EDT_ERR_ARG (bad pointers,
+ * min > max), EDT_ERR_WORKSPACE. */
 int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, const float* pts,
-                       int64_t n, const float* T_map_sensor, const uint8_t* exclude,
-                       const edt_logodds_t* params, void* ws, size_t ws_bytes, void* stream);
+                       int64_t n, const float* T_map_sensor, const uint8_t* keep,
+                       const uint8_t* exclude, const edt_logodds_t* params, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/*
+ * edt_outlier_filter -- statistical outlier filtering of a raw cloud before
+ * insertion (Sec. III-A: points are filtered by their Euclidean distance to
+ * their neighbours).  For every finite point i (all three coordinates
+ * finite), in float32 with one rounding per operation:
+ *   s_ij = (dx*dx + dy*dy) + dz*dz for the differences p_j - p_i, j != i;
+ *   the neighbours are the finite j with s_ij <= radius*radius, of which the
+ *   k closest count (m of them, m <= k);
+ *   d_i = (sum of sqrtf(s_ij) over them in ascending order + (k - m) *
+ *         radius) / k   -- a missing neighbour counts as radius.
+ * mu and the sample standard deviation sigma of d_i over the finite points
+ * come from exact fixed-point sums (d_i in units of 2^-40, d_i^2 in units of
+ * 2^-48), so they do not depend on the order of accumulation; keep[i] = 1
+ * iff point i is finite and d_i <= mu + alpha * sigma (double).  The
+ * neighbour search is exact for coordinates within about 80 m of the
+ * sensor origin (cells of 1.001 radius).
+ *   pts        device float32 [n][3], sensor frame; n <= EDT_OUTLIER_MAX_POINTS
+ *   k          1..16 neighbours
+ *   keep       device uint8 [n] out
+ *   mean_dist  device float32 [n] out (nullable): d_i, NaN for non-finite
+ *   stats      device float64 [3] out (nullable): mu, sigma, threshold
+ *   ws         device workspace of edt_outlier_workspace_bytes(n) bytes
+ * Errors: EDT_ERR_ARG, EDT_ERR_WORKSPACE.  No synchronisation; fill
+ * kernels only, graph-capturable.
+ */
+#define EDT_OUTLIER_MAX_POINTS 4194304
+size_t edt_outlier_workspace_bytes(int64_t n_points);
+int edt_outlier_filter(const float* pts, int64_t n, int32_t k, float radius, float alpha,
+                       uint8_t* keep, float* mean_dist, double* stats, void* ws, size_t ws_bytes,
+                       void* stream);
 
 /*
  * edt_insert_links -- insert the robot's voxelized links placed by joint

@@ -64,11 +64,14 @@ def _load():
         lib.oracle_ray_walk.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_ray_walk.restype = ctypes.c_int
         lib.oracle_update_logodds.argtypes = ([ctypes.c_int] * 3 + [P, ctypes.c_float, P, P, P,
-                                              ctypes.c_int64, P, P] + [ctypes.c_int] * 5)
+                                              ctypes.c_int64, P, P, P] + [ctypes.c_int] * 5)
         lib.oracle_update_logodds.restype = None
         lib.oracle_outlier_filter.argtypes = [P, ctypes.c_int64, ctypes.c_int, ctypes.c_float,
                                               ctypes.c_double, P, P, P]
         lib.oracle_outlier_filter.restype = None
+        lib.oracle_outlier_mean_dist.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int,
+                                                 ctypes.c_float, P]
+        lib.oracle_outlier_mean_dist.restype = None
         _lib = lib
     return _lib
 
@@ -166,7 +169,7 @@ LOGODDS_DEFAULT = dict(hit=85, miss=-41, lmin=-200, lmax=350, threshold=0)
 
 def update_logodds(grid, logodds: np.ndarray, occ: np.ndarray, pts: np.ndarray, T: np.ndarray,
                    exclude: np.ndarray | None = None, hit=85, miss=-41, lmin=-200, lmax=350,
-                   threshold=0):
+                   threshold=0, keep: np.ndarray | None = None):
     """One frame's Bayesian occupancy update (Sec. III-A), in place on the
     int16 log-odds grid; occ (uint8) becomes logodds > threshold."""
     nx, ny, nz, origin, v = _grid_args(grid)
@@ -175,8 +178,11 @@ def update_logodds(grid, logodds: np.ndarray, occ: np.ndarray, pts: np.ndarray, 
     assert logodds.dtype == np.int16 and logodds.flags.c_contiguous and logodds.size == grid.n
     assert occ.dtype == np.uint8 and occ.flags.c_contiguous and occ.size == grid.n
     ex = None if exclude is None else np.ascontiguousarray(exclude, np.uint8)
+    kp = None if keep is None else np.ascontiguousarray(keep, np.uint8)
+    assert kp is None or kp.size == pts.shape[0]
     _load().oracle_update_logodds(nx, ny, nz, _ptr(origin), v, _ptr(logodds), _ptr(occ), _ptr(pts),
-                                  pts.shape[0], _ptr(T), None if ex is None else _ptr(ex),
+                                  pts.shape[0], _ptr(T), None if kp is None else _ptr(kp),
+                                  None if ex is None else _ptr(ex),
                                   int(hit), int(miss), int(lmin), int(lmax), int(threshold))
     return logodds, occ
 
@@ -194,3 +200,14 @@ def outlier_filter(pts: np.ndarray, k: int = 8, radius: float = 0.01, alpha: flo
     _load().oracle_outlier_filter(_ptr(pts), n, int(k), float(radius), float(alpha), _ptr(keep),
                                   _ptr(dm), _ptr(stats))
     return keep, dm, tuple(float(x) for x in stats)
+
+
+def outlier_mean_dist(pts: np.ndarray, idx: np.ndarray, k: int = 8, radius: float = 0.01):
+    """The outlier filter's mean neighbour distance d_i for the listed points
+    only (same definition as outlier_filter, O(len(idx) * n))."""
+    pts = np.ascontiguousarray(pts, np.float32).reshape(-1, 3)
+    idx = np.ascontiguousarray(idx, np.int64)
+    out = np.zeros(idx.size, np.float32)
+    _load().oracle_outlier_mean_dist(_ptr(pts), pts.shape[0], _ptr(idx), idx.size, int(k),
+                                     float(radius), _ptr(out))
+    return out

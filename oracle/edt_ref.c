@@ -342,7 +342,8 @@ int oracle_max_threads(void)
 /* some sensor ray crosses on its way to an endpoint (and that holds no     */
 /* endpoint) gets one miss update, each clamped to [lmin, lmax]; the voxel  */
 /* is occupied iff its log-odds exceed the threshold.  Only points whose    */
-/* endpoint voxel lies in the map and is not excluded take part.           */
+/* endpoint voxel lies in the map and is not excluded (and, given a keep   */
+/* mask, that the filter kept) take part.                                   */
 /*                                                                          */
 /* The ray from the sensor voxel to the endpoint voxel is walked one voxel  */
 /* at a time (the incremental traversal of Amanatides and Woo): in voxel    */
@@ -405,8 +406,8 @@ int oracle_ray_walk(const float* a, const float* b, int32_t* out, int max_out)
 
 void oracle_update_logodds(int nx, int ny, int nz, const float* origin, float voxel,
                            int16_t* logodds, uint8_t* occ, const float* pts, int64_t n,
-                           const float* T, const uint8_t* exclude, int hit, int miss,
-                           int lmin, int lmax, int threshold)
+                           const float* T, const uint8_t* keep, const uint8_t* exclude, int hit,
+                           int miss, int lmin, int lmax, int threshold)
 {
     const int64_t nvox = (int64_t)nx * ny * nz;
     uint8_t* is_hit = (uint8_t*)calloc((size_t)nvox, 1);
@@ -416,6 +417,7 @@ void oracle_update_logodds(int nx, int ny, int nz, const float* origin, float vo
     float a[3];
     for (int i = 0; i < 3; ++i) a[i] = (T[4 * i + 3] - origin[i]) / voxel;
     for (int64_t k = 0; k < n; ++k) {
+        if (keep && !keep[k]) continue;   /* filtered out before insertion */
         const float* p = pts + 3 * k;
         float m[3], b[3];
         int e[3], ok = 1;
@@ -498,43 +500,55 @@ static int finite3(const float* p)
     return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
 }
 
+/* d_i of the listed points only (the same definition, O(m n)). */
+static float outlier_mean_one(const float* pts, int64_t n, int64_t i, int k, float R);
+
+void oracle_outlier_mean_dist(const float* pts, int64_t n, const int64_t* idx, int64_t m, int k,
+                              float R, float* out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; ++t) out[t] = outlier_mean_one(pts, n, idx[t], k, R);
+}
+
+static float outlier_mean_one(const float* pts, int64_t n, int64_t i, int k, float R)
+{
+    const float rr = R * R;
+    const float* p = pts + 3 * i;
+    if (!finite3(p)) return NAN;
+    float best[64];
+    int m = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const float* q = pts + 3 * j;
+        if (!finite3(q)) continue;
+        const float dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
+        const float s = (dx * dx + dy * dy) + dz * dz;
+        if (!(s <= rr)) continue;
+        if (m < k) {
+            int t = m++;
+            while (t > 0 && best[t - 1] > s) { best[t] = best[t - 1]; --t; }
+            best[t] = s;
+        } else if (s < best[k - 1]) {
+            int t = k - 1;
+            while (t > 0 && best[t - 1] > s) { best[t] = best[t - 1]; --t; }
+            best[t] = s;
+        }
+    }
+    float acc = 0.0f;
+    for (int t = 0; t < m; ++t) acc = acc + sqrtf(best[t]);
+    acc = acc + (float)(k - m) * R;
+    return acc / (float)k;
+}
+
 void oracle_outlier_filter(const float* pts, int64_t n, int k, float R, double alpha,
                            uint8_t* keep, float* dmean, double* stats)
 {
-    const float rr = R * R;
     int64_t S1 = 0, S2 = 0, cnt = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : S1, S2, cnt)
     for (int64_t i = 0; i < n; ++i) {
-        const float* p = pts + 3 * i;
-        if (!finite3(p)) {
-            dmean[i] = NAN;
-            continue;
-        }
-        float best[64];
-        int m = 0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            const float* q = pts + 3 * j;
-            if (!finite3(q)) continue;
-            const float dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
-            const float s = (dx * dx + dy * dy) + dz * dz;
-            if (!(s <= rr)) continue;
-            /* keep the k smallest, sorted ascending */
-            if (m < k) {
-                int t = m++;
-                while (t > 0 && best[t - 1] > s) { best[t] = best[t - 1]; --t; }
-                best[t] = s;
-            } else if (s < best[k - 1]) {
-                int t = k - 1;
-                while (t > 0 && best[t - 1] > s) { best[t] = best[t - 1]; --t; }
-                best[t] = s;
-            }
-        }
-        float acc = 0.0f;
-        for (int t = 0; t < m; ++t) acc = acc + sqrtf(best[t]);
-        acc = acc + (float)(k - m) * R;
-        const float d = acc / (float)k;
+        const float d = outlier_mean_one(pts, n, i, k, R);
         dmean[i] = d;
+        if (!finite3(pts + 3 * i)) continue;
         const double dd = (double)d;
         S1 += (int64_t)rint(dd * 1099511627776.0);             /* 2^40 */
         S2 += (int64_t)rint(dd * dd * 281474976710656.0);      /* 2^48 */

@@ -79,11 +79,13 @@ __global__ void k_insert_points(GridArgs g, const float* __restrict__ pts, int64
 // voxels to cross, x before y before z on ties, so it ends exactly on the
 // endpoint voxel.  float32, one rounding per operation, no contraction.
 __global__ void k_logodds_rays(GridArgs g, const float* __restrict__ pts, int64_t n,
-                               const float* __restrict__ T, const uint8_t* __restrict__ exclude,
-                               uint8_t* __restrict__ hit, uint8_t* __restrict__ fre)
+                               const float* __restrict__ T, const uint8_t* __restrict__ keep,
+                               const uint8_t* __restrict__ exclude, uint8_t* __restrict__ hit,
+                               uint8_t* __restrict__ fre)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (keep && !keep[i]) return;
     float t[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) t[k] = T[k];
@@ -418,8 +420,8 @@ int edt_logodds_reset(const edt_grid_t* grid, int16_t* logodds, void* ws, size_t
 }
 
 int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, const float* pts,
-                       int64_t n, const float* T, const uint8_t* exclude, const edt_logodds_t* params,
-                       void* ws, size_t ws_bytes, void* stream)
+                       int64_t n, const float* T, const uint8_t* keep, const uint8_t* exclude,
+                       const edt_logodds_t* params, void* ws, size_t ws_bytes, void* stream)
 {
     int rc = check_grid(grid);
     if (rc) return rc;
@@ -447,7 +449,7 @@ int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, c
     uint8_t* fre = hit + nv;
     if (n > 0) {
         hipLaunchKernelGGL(k_logodds_rays, dim3((unsigned)blocks), dim3(256), 0, st, grid_args(grid),
-                           pts, n, T, exclude, hit, fre);
+                           pts, n, T, keep, exclude, hit, fre);
         if ((rc = check_launch("k_logodds_rays"))) return rc;
     }
     const LogOdds p{params->hit, params->miss, params->min, params->max, params->threshold};

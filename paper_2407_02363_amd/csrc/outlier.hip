@@ -1,0 +1,332 @@
+// Statistical outlier filtering of a raw point cloud (Sec. III-A: the
+// points are filtered by their Euclidean distance to their neighbours).
+//
+// Per finite point i: d_i = mean distance to its k nearest other points
+// within radius R, a missing neighbour counting as R; over the finite
+// points mu and the sample standard deviation sigma of d_i (exact
+// fixed-point sums, so independent of the order of accumulation); keep i
+// iff d_i <= mu + alpha * sigma.
+//
+// Neighbour search: a hash grid of cells slightly larger than R (1.001 R),
+// so every neighbour within R lies in the 3 x 3 x 3 cells around a point
+// for coordinates below about 80 m.  Points are counted per hash bucket,
+// the counts are scanned into bucket offsets, and the points are scattered
+// into their buckets; a query walks the 27 cells' buckets and keeps only
+// candidates whose own cell is the one visited (several cells may share a
+// bucket).  The k smallest squared distances are kept sorted in registers
+// by a compare-exchange pass per candidate.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "common.h"
+
+namespace edtmi {
+namespace {
+
+constexpr int KMAX = 16;
+constexpr double SCALE1 = 1099511627776.0;   // 2^40: units of d
+constexpr double SCALE2 = 281474976710656.0; // 2^48: units of d^2
+
+struct SorLayout {
+    size_t count, start, cursor, sums, spts, acc, total;
+    unsigned tmask;
+    int nsums;
+};
+
+// hash-table size: a power of two >= 2 n, at least 1024, at most 2^23
+__host__ inline SorLayout sor_layout(int64_t n)
+{
+    int64_t T = 1024;
+    while (T < 2 * n && T < (int64_t(1) << 23)) T <<= 1;
+    SorLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.count = take((size_t)T * 4);
+    L.start = take((size_t)T * 4);
+    L.cursor = take((size_t)T * 4);
+    L.nsums = (int)(T / 1024);
+    L.sums = take((size_t)L.nsums * 4);
+    L.spts = take((size_t)std::max<int64_t>(n, 1) * 16);
+    L.acc = take(4 * 8);
+    L.total = o;
+    L.tmask = (unsigned)(T - 1);
+    return L;
+}
+
+__device__ __forceinline__ bool finite3(float x, float y, float z)
+{
+    return __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z);
+}
+
+__device__ __forceinline__ int cell_of(float x, float h)
+{
+    const float c = floorf(x / h);
+    return (int)fminf(fmaxf(c, -1.0e9f), 1.0e9f);
+}
+
+__device__ __forceinline__ unsigned bucket(int ix, int iy, int iz, unsigned mask)
+{
+    return (((unsigned)ix * 73856093u) ^ ((unsigned)iy * 19349663u) ^ ((unsigned)iz * 83492791u)) & mask;
+}
+
+__global__ void k_sor_zero(unsigned* __restrict__ count, unsigned* __restrict__ cursor, int T,
+                           unsigned long long* __restrict__ acc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < T) {
+        count[i] = 0u;
+        cursor[i] = 0u;
+    }
+    if (i < 4) acc[i] = 0ull;
+}
+
+__global__ void k_sor_count(const float* __restrict__ pts, int64_t n, float h, unsigned mask,
+                            unsigned* __restrict__ count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+    if (!finite3(x, y, z)) return;
+    atomicAdd(count + bucket(cell_of(x, h), cell_of(y, h), cell_of(z, h), mask), 1u);
+}
+
+// exclusive scan of T counts (T a multiple of 1024): per-block scan of 1024
+// values (4 per thread), one block scanning the block totals, then the add
+__global__ __launch_bounds__(256) void k_scan_blocks(const unsigned* __restrict__ in,
+                                                     unsigned* __restrict__ out,
+                                                     unsigned* __restrict__ sums)
+{
+    __shared__ unsigned s[256];
+    const int base = blockIdx.x * 1024 + 4 * threadIdx.x;
+    const uint4 v = *reinterpret_cast<const uint4*>(in + base);
+    const unsigned t = v.x + v.y + v.z + v.w;
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const unsigned ex = s[threadIdx.x] - t;
+    *reinterpret_cast<uint4*>(out + base) = make_uint4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
+    if (threadIdx.x == 255) sums[blockIdx.x] = s[255];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(unsigned* __restrict__ sums, int nb)
+{
+    __shared__ unsigned s[1024];
+    const int per = (nb + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    unsigned t = 0;
+    for (int j = 0; j < per; ++j)
+        if (b0 + j < nb) t += sums[b0 + j];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    unsigned run = s[threadIdx.x] - t;
+    for (int j = 0; j < per; ++j)
+        if (b0 + j < nb) {
+            const unsigned c = sums[b0 + j];
+            sums[b0 + j] = run;
+            run += c;
+        }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(unsigned* __restrict__ out,
+                                                  const unsigned* __restrict__ sums)
+{
+    const unsigned add = sums[blockIdx.x];
+    uint4* p = reinterpret_cast<uint4*>(out + blockIdx.x * 1024 + 4 * threadIdx.x);
+    uint4 v = *p;
+    v.x += add;
+    v.y += add;
+    v.z += add;
+    v.w += add;
+    *p = v;
+}
+
+__global__ void k_sor_scatter(const float* __restrict__ pts, int64_t n, float h, unsigned mask,
+                              const unsigned* __restrict__ start, unsigned* __restrict__ cursor,
+                              float4* __restrict__ spts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+    if (!finite3(x, y, z)) return;
+    const unsigned b = bucket(cell_of(x, h), cell_of(y, h), cell_of(z, h), mask);
+    const unsigned pos = start[b] + atomicAdd(cursor + b, 1u);
+    spts[pos] = make_float4(x, y, z, __int_as_float((int)i));
+}
+
+__global__ __launch_bounds__(256) void k_sor_knn(const float* __restrict__ pts, int64_t n, int k,
+                                                 float R, float h, unsigned mask,
+                                                 const unsigned* __restrict__ start,
+                                                 const unsigned* __restrict__ count,
+                                                 const float4* __restrict__ spts,
+                                                 float* __restrict__ dmean,
+                                                 unsigned long long* __restrict__ acc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
+    if (!finite3(px, py, pz)) {
+        dmean[i] = __builtin_nanf("");
+        return;
+    }
+    const float rr = R * R;
+    const int cx = cell_of(px, h), cy = cell_of(py, h), cz = cell_of(pz, h);
+    float best[KMAX];
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t) best[t] = __builtin_huge_valf();
+    int found = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int ncx = cx + dx, ncy = cy + dy, ncz = cz + dz;
+                const unsigned b = bucket(ncx, ncy, ncz, mask);
+                const unsigned e1 = start[b] + count[b];
+                for (unsigned e = start[b]; e < e1; ++e) {
+                    const float4 q = spts[e];
+                    if (__float_as_int(q.w) == (int)i) continue;
+                    if (cell_of(q.x, h) != ncx || cell_of(q.y, h) != ncy || cell_of(q.z, h) != ncz)
+                        continue;
+                    const float ex = q.x - px, ey = q.y - py, ez = q.z - pz;
+                    float s = (ex * ex + ey * ey) + ez * ez;
+                    if (!(s <= rr)) continue;
+                    ++found;
+                    // one compare-exchange pass keeps best[] sorted ascending
+#pragma unroll
+                    for (int t = 0; t < KMAX; ++t) {
+                        const float lo = fminf(best[t], s), hi = fmaxf(best[t], s);
+                        best[t] = lo;
+                        s = hi;
+                    }
+                }
+            }
+    const int m = min(found, k);
+    float sum = 0.0f;
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t)
+        if (t < m) sum = sum + sqrtf(best[t]);
+    sum = sum + (float)(k - m) * R;
+    const float d = sum / (float)k;
+    dmean[i] = d;
+    const double dd = (double)d;
+    atomicAdd(acc + 0, (unsigned long long)(long long)rint(dd * SCALE1));
+    atomicAdd(acc + 1, (unsigned long long)(long long)rint(dd * dd * SCALE2));
+    atomicAdd(acc + 2, 1ull);
+}
+
+__device__ __forceinline__ double sor_threshold(const unsigned long long* acc, double alpha,
+                                                double* mu_out, double* sigma_out)
+{
+    const long long S1 = (long long)acc[0], S2 = (long long)acc[1], cnt = (long long)acc[2];
+    double mu = 0.0, sigma = 0.0;
+    if (cnt > 0) mu = (double)S1 / SCALE1 / (double)cnt;
+    if (cnt > 1) {
+        const double var = ((double)S2 / SCALE2 - (double)cnt * mu * mu) / (double)(cnt - 1);
+        sigma = var > 0.0 ? sqrt(var) : 0.0;
+    }
+    *mu_out = mu;
+    *sigma_out = sigma;
+    return mu + alpha * sigma;
+}
+
+__global__ void k_sor_keep(const float* __restrict__ pts, int64_t n, const float* __restrict__ dmean,
+                           const unsigned long long* __restrict__ acc, double alpha,
+                           uint8_t* __restrict__ keep, double* __restrict__ stats)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double mu, sigma;
+    const double thr = sor_threshold(acc, alpha, &mu, &sigma);
+    if (i == 0 && stats) {
+        stats[0] = mu;
+        stats[1] = sigma;
+        stats[2] = thr;
+    }
+    if (i >= n) return;
+    const bool fin = finite3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
+    keep[i] = fin && (double)dmean[i] <= thr ? 1 : 0;
+}
+
+}  // namespace
+}  // namespace edtmi
+
+using namespace edtmi;
+
+extern "C" {
+
+size_t edt_outlier_workspace_bytes(int64_t n_points)
+{
+    if (n_points < 0 || n_points > EDT_OUTLIER_MAX_POINTS) return 0;
+    return sor_layout(n_points).total + (size_t)std::max<int64_t>(n_points, 1) * 4;
+}
+
+int edt_outlier_filter(const float* pts, int64_t n, int32_t k, float radius, float alpha,
+                       uint8_t* keep, float* mean_dist, double* stats, void* ws, size_t ws_bytes,
+                       void* stream)
+{
+    if (n < 0 || n > EDT_OUTLIER_MAX_POINTS || (n > 0 && (!pts || !keep)) || !ws) {
+        set_error("edt_outlier_filter: bad pointer or point count (0..%d)", EDT_OUTLIER_MAX_POINTS);
+        return EDT_ERR_ARG;
+    }
+    if (k < 1 || k > KMAX || !(radius > 0.0f) || !std::isfinite(radius) || !std::isfinite(alpha)) {
+        set_error("edt_outlier_filter: need 1 <= k <= %d, a finite radius > 0 and a finite alpha", KMAX);
+        return EDT_ERR_ARG;
+    }
+    if (ws_bytes < edt_outlier_workspace_bytes(n)) {
+        set_error("edt_outlier_filter: workspace of %zu bytes is below %zu", ws_bytes,
+                  edt_outlier_workspace_bytes(n));
+        return EDT_ERR_WORKSPACE;
+    }
+    const SorLayout L = sor_layout(n);
+    char* w = static_cast<char*>(ws);
+    unsigned* count = reinterpret_cast<unsigned*>(w + L.count);
+    unsigned* start = reinterpret_cast<unsigned*>(w + L.start);
+    unsigned* cursor = reinterpret_cast<unsigned*>(w + L.cursor);
+    unsigned* sums = reinterpret_cast<unsigned*>(w + L.sums);
+    float4* spts = reinterpret_cast<float4*>(w + L.spts);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(w + L.acc);
+    float* dm = mean_dist ? mean_dist : reinterpret_cast<float*>(w + L.total);
+    const int T = (int)L.tmask + 1;
+    const float h = radius * 1.001f;
+    const hipStream_t st = as_stream(stream);
+    const unsigned pblocks = (unsigned)((std::max<int64_t>(n, 1) + 255) / 256);
+    hipLaunchKernelGGL(k_sor_zero, dim3((T + 255) / 256), dim3(256), 0, st, count, cursor, T, acc);
+    int rc = check_launch("k_sor_zero");
+    if (rc) return rc;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_sor_count, dim3(pblocks), dim3(256), 0, st, pts, n, h, L.tmask, count);
+        if ((rc = check_launch("k_sor_count"))) return rc;
+    }
+    hipLaunchKernelGGL(k_scan_blocks, dim3(L.nsums), dim3(256), 0, st, count, start, sums);
+    if ((rc = check_launch("k_scan_blocks"))) return rc;
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, L.nsums);
+    if ((rc = check_launch("k_scan_sums"))) return rc;
+    hipLaunchKernelGGL(k_scan_add, dim3(L.nsums), dim3(256), 0, st, start, sums);
+    if ((rc = check_launch("k_scan_add"))) return rc;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_sor_scatter, dim3(pblocks), dim3(256), 0, st, pts, n, h, L.tmask, start,
+                           cursor, spts);
+        if ((rc = check_launch("k_sor_scatter"))) return rc;
+        hipLaunchKernelGGL(k_sor_knn, dim3(pblocks), dim3(256), 0, st, pts, n, (int)k, radius, h,
+                           L.tmask, start, count, spts, dm, acc);
+        if ((rc = check_launch("k_sor_knn"))) return rc;
+    }
+    hipLaunchKernelGGL(k_sor_keep, dim3(pblocks), dim3(256), 0, st, pts, n, dm, acc, (double)alpha,
+                       keep, stats);
+    return check_launch("k_sor_keep");
+}
+
+}  // extern "C"

@@ -66,7 +66,7 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_query_spheres", "edt_compute_stage", "edt_default_tuning", "edt_compute_tuned",
             "edt_autotune", "edt_batch_workspace_bytes", "edt_compute_batched", "edt_batch_status",
             "edt_compute_many", "edt_logodds_workspace_bytes", "edt_logodds_reset",
-            "edt_update_logodds",
+            "edt_update_logodds", "edt_outlier_workspace_bytes", "edt_outlier_filter",
             "edt_autotune_batched"]
 
 BATCH_MAX = 48
@@ -105,8 +105,11 @@ def lib():
         "edt_compute_many": ([P, i32, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_logodds_workspace_bytes": ([G], ctypes.c_size_t),
         "edt_logodds_reset": ([G, P, P, ctypes.c_size_t, P], ctypes.c_int),
-        "edt_update_logodds": ([G, P, P, P, i64, P, P, ctypes.POINTER(LogOdds), P, ctypes.c_size_t, P],
-                               ctypes.c_int),
+        "edt_update_logodds": ([G, P, P, P, i64, P, P, P, ctypes.POINTER(LogOdds), P, ctypes.c_size_t,
+                                P], ctypes.c_int),
+        "edt_outlier_workspace_bytes": ([i64], ctypes.c_size_t),
+        "edt_outlier_filter": ([P, i64, i32, ctypes.c_float, ctypes.c_float, P, P, P, P,
+                                ctypes.c_size_t, P], ctypes.c_int),
         "edt_batch_status": ([P, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
         "edt_autotune_batched": ([P, i32, P, ctypes.c_size_t, i32, ctypes.POINTER(Tuning),
                                   ctypes.POINTER(ctypes.c_float), P], ctypes.c_int),
@@ -341,7 +344,7 @@ def edt_logodds_reset(grid, logodds, ws, stream=None):
 
 
 def edt_update_logodds(grid, logodds, occ, pts, T_map_sensor, ws, exclude=None,
-                       params=LOGODDS_DEFAULT, stream=None):
+                       params=LOGODDS_DEFAULT, keep=None, stream=None):
     """params: (hit, miss, min, max, threshold) in the log-odds units."""
     g = make_grid(grid)
     n = pts.shape[0] if pts.dim() == 2 else pts.numel() // 3
@@ -350,6 +353,31 @@ def edt_update_logodds(grid, logodds, occ, pts, T_map_sensor, ws, exclude=None,
                                     _dev(occ, torch.uint8, "occ", _n(g)),
                                     _dev(pts, torch.float32, "pts", 3 * n), n,
                                     _dev(T_map_sensor, torch.float32, "T_map_sensor", 12),
+                                    _dev(keep, torch.uint8, "keep", n),
                                     _dev(exclude, torch.uint8, "exclude", _n(g)), ctypes.byref(p),
                                     _dev(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)),
            "edt_update_logodds")
+
+
+OUTLIER_MAX_POINTS = 4194304
+
+
+def edt_outlier_workspace_bytes(n_points: int) -> int:
+    return int(lib().edt_outlier_workspace_bytes(int(n_points)))
+
+
+def new_outlier_workspace(n_points: int, device="cuda"):
+    return torch.empty(edt_outlier_workspace_bytes(n_points), dtype=torch.uint8, device=device)
+
+
+def edt_outlier_filter(pts, keep, ws, k=8, radius=0.01, alpha=1.0, mean_dist=None, stats=None,
+                       stream=None):
+    """pts float32 [n, 3] (device); keep uint8 [n] out; mean_dist float32 [n]
+    and stats float64 [3] (mu, sigma, threshold) optional outputs."""
+    n = pts.shape[0]
+    _check(lib().edt_outlier_filter(_dev(pts, torch.float32, "pts", 3 * n), n, int(k), float(radius),
+                                    float(alpha), _dev(keep, torch.uint8, "keep", n),
+                                    _dev(mean_dist, torch.float32, "mean_dist", n),
+                                    _dev(stats, torch.float64, "stats", 3),
+                                    _dev(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)),
+           "edt_outlier_filter")

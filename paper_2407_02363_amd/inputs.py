@@ -467,6 +467,20 @@ class CycleInputs:
     joint_states: np.ndarray  # float64 [n_cycles, 7]
 
 
+def with_outliers(points: np.ndarray, frac: float, seed: int, nan_frac: float = 0.0) -> np.ndarray:
+    """Copy of a camera-frame cloud in which a fraction frac of the points are
+    moved along their own ray to a random 30-90% of their depth (the flying
+    pixels of depth cameras) and a fraction nan_frac become NaN (no return)."""
+    g = rng(seed)
+    out = np.array(points, np.float32, copy=True)
+    n = out.shape[0]
+    idx = g.choice(n, int(round(frac * n)), replace=False)
+    out[idx] *= g.uniform(0.3, 0.9, (idx.size, 1)).astype(np.float32)
+    if nan_frac > 0:
+        out[g.choice(n, int(round(nan_frac * n)), replace=False)] = np.nan
+    return out
+
+
 def cycle_inputs(seed: int = 0, n_frames: int = 4, n_states: int = 16,
                  grid: Grid = CYCLE_GRID) -> CycleInputs:
     cam = Camera()

@@ -101,13 +101,23 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.edt_logodds_workspace_bytes(ctypes.byref(ok)) >= 2 * ok.nx * ok.ny * ok.nz
     lo = edt.LogOdds(85, -41, 10, -10, 0, 0)
     wsb = lib.edt_logodds_workspace_bytes(ctypes.byref(ok))
-    assert lib.edt_update_logodds(ctypes.byref(ok), one, one, one, 1, one, None, ctypes.byref(lo),
-                                  one, wsb, None) == -1
+    assert lib.edt_update_logodds(ctypes.byref(ok), one, one, one, 1, one, None, None,
+                                  ctypes.byref(lo), one, wsb, None) == -1
     lo = edt.LogOdds(*edt.LOGODDS_DEFAULT, 0)
-    assert lib.edt_update_logodds(ctypes.byref(ok), one, one, one, 1, one, None, ctypes.byref(lo),
-                                  one, wsb - 1, None) == -3
-    assert lib.edt_update_logodds(ctypes.byref(ok), one, None, one, 1, one, None, ctypes.byref(lo),
-                                  one, wsb, None) == -1
+    assert lib.edt_update_logodds(ctypes.byref(ok), one, one, one, 1, one, None, None,
+                                  ctypes.byref(lo), one, wsb - 1, None) == -3
+    assert lib.edt_update_logodds(ctypes.byref(ok), one, None, one, 1, one, None, None,
+                                  ctypes.byref(lo), one, wsb, None) == -1
+    # outlier filter: k, radius, point count and workspace before any launch
+    ow = lib.edt_outlier_workspace_bytes(1000)
+    assert ow > 16 * 1000 and lib.edt_outlier_workspace_bytes(edt.OUTLIER_MAX_POINTS + 1) == 0
+    assert lib.edt_outlier_filter(one, 1000, 0, 0.01, 1.0, one, None, None, one, ow, None) == -1
+    assert lib.edt_outlier_filter(one, 1000, 17, 0.01, 1.0, one, None, None, one, ow, None) == -1
+    assert lib.edt_outlier_filter(one, 1000, 8, 0.0, 1.0, one, None, None, one, ow, None) == -1
+    assert lib.edt_outlier_filter(one, 1000, 8, 0.01, float("nan"), one, None, None, one, ow,
+                                  None) == -1
+    assert lib.edt_outlier_filter(one, 1000, 8, 0.01, 1.0, one, None, None, one, ow - 1, None) == -3
+    assert lib.edt_outlier_filter(one, -1, 8, 0.01, 1.0, one, None, None, one, ow, None) == -1
     assert lib.edt_logodds_reset(ctypes.byref(ok), one, one, 16, None) == -3
     huge = edt.EdtGrid(8, 1024, 8, (ctypes.c_float * 3)(0, 0, 0), 0.01)
     assert lib.edt_compute_tuned(ctypes.byref(huge), one, one, one,
