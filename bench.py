@@ -222,57 +222,72 @@ def batched_workload(args, torch, edt, inputs, host_latency=True):
 
 def occupancy_workload(args, torch, edt, ci, cyc):
     """Probabilistic occupancy front end on the control-cycle map: the
-    per-frame log-odds update alone (ray walks + voxel update), and the cycle
-    with the environment map built from the persistent log-odds grid instead
-    of plain insertion."""
+    statistical outlier filter and the per-frame log-odds update (ray walks
+    + voxel update) alone, and the cycle with the environment map built from
+    filtered frames through the persistent log-odds grid instead of plain
+    insertion."""
+    from paper_2407_02363_amd import inputs
     g = ci.grid
     dev = cyc.dev
     L = torch.zeros(g.n, dtype=torch.int16, device=dev)
     occ = torch.zeros(g.n, dtype=torch.uint8, device=dev)
     ws = edt.new_logodds_workspace(g, dev)
     edt.edt_logodds_reset(g, L, ws)
-    frames = cyc.frames
-    nf = frames.shape[0]
+    # the cycle's frames with 1% flying pixels and 0.2% missing returns
+    frames = torch.stack([torch.from_numpy(inputs.with_outliers(f, 0.01, 100 + i, 0.002))
+                          for i, f in enumerate(ci.frames)]).to(dev)
+    nf, npts = frames.shape[0], frames.shape[1]
+    keep = torch.empty(npts, dtype=torch.uint8, device=dev)
+    sws = edt.new_outlier_workspace(npts, dev)
+    sor_k, sor_r, sor_a = 8, 0.01, 1.0
+    maps = edt.batch_maps([g, g], [occ, cyc.occ_self], [cyc.d2_env, cyc.d2_self],
+                          [cyc.site_env, cyc.site_self])
+
+    def sor(k):
+        edt.edt_outlier_filter(frames[k % nf], keep, sws, k=sor_k, radius=sor_r, alpha=sor_a)
 
     def update(k):
-        edt.edt_update_logodds(g, L, occ, frames[k % nf], cyc.T, ws, exclude=cyc.occ_self)
-
-    for k in range(5):
-        update(k)
-    torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    reps = max(50, args.steps // 4)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(st)
-    for k in range(reps):
-        update(k)
-    b.record(st)
-    b.synchronize()
-    ms = a.elapsed_time(b) / reps
+        edt.edt_update_logodds(g, L, occ, frames[k % nf], cyc.T, ws, exclude=cyc.occ_self, keep=keep)
 
     def cycle(k):
         s = k % cyc.n_states
         edt.edt_clear(g, cyc.occ_self)
         edt.edt_insert_links(g, cyc.occ_self, cyc.link_pts, cyc.link_off, cyc.poses[s], cyc.self_mask)
+        sor(k)
         update(k)
-        edt.edt_compute_many(edt.batch_maps([g, g], [occ, cyc.occ_self], [cyc.d2_env, cyc.d2_self],
-                                            [cyc.site_env, cyc.site_self]))
+        edt.edt_compute_many(maps)
         edt.edt_query_spheres(g, cyc.d2_env, cyc.site_env, cyc.centres[s], cyc.radii, cyc.out_env)
         edt.edt_query_spheres(g, cyc.d2_self, cyc.site_self, cyc.centres[s], cyc.radii, cyc.out_self)
 
-    for k in range(5):
-        cycle(k)
+    st = torch.cuda.current_stream()
+
+    def avg_ms(fn, reps):
+        for k in range(5):
+            fn(k)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for k in range(reps):
+            fn(k)
+        b.record(st)
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(50, args.steps // 4)
+    sor_ms = avg_ms(sor, reps)
+    upd_ms = avg_ms(update, reps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         cycle(k)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    return {"workload": "256x256x128 map at 1 cm, persistent int16 log-odds, one 307200-point frame "
-                        "per update (hit 85, miss -41, clamp [-200, 350] hundredths of a nat), "
-                        "robot voxels excluded, every ray walked from the camera",
-            "update_ms": ms, "points_per_s": frames.shape[1] / (ms * 1e-3),
+    return {"workload": f"256x256x128 map at 1 cm; {npts}-point frames with 1% flying pixels and 0.2% "
+                        f"missing returns; outlier filter k={sor_k}, radius {sor_r} m, alpha {sor_a}; "
+                        "persistent int16 log-odds (hit 85, miss -41, clamp [-200, 350] hundredths "
+                        "of a nat), robot voxels excluded, every ray walked from the camera",
+            "outlier_filter_ms": sor_ms, "outlier_kept": float(keep.float().mean().item()),
+            "logodds_update_ms": upd_ms, "points_per_s": npts / (upd_ms * 1e-3),
             "cycle_eager_ms": 1e3 * el / args.steps,
             "cycle_mvox_s": 2 * g.n * args.steps / el / 1e6,
             "occupied_voxels": int(occ.sum().item())}

@@ -11,10 +11,9 @@
 // so every neighbour within R lies in the 3 x 3 x 3 cells around a point
 // for coordinates below about 80 m.  Points are counted per hash bucket,
 // the counts are scanned into bucket offsets, and the points are scattered
-// into their buckets; a query walks the 27 cells' buckets and keeps only
-// candidates whose own cell is the one visited (several cells may share a
-// bucket).  The k smallest squared distances are kept sorted in registers
-// by a compare-exchange pass per candidate.
+// into their buckets; a query walks the 27 cells' buckets, each once.  The
+// k smallest squared distances are kept sorted in registers by a
+// compare-exchange pass per candidate.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -169,6 +168,16 @@ __global__ void k_sor_scatter(const float* __restrict__ pts, int64_t n, float h,
     spts[pos] = make_float4(x, y, z, __int_as_float((int)i));
 }
 
+// One thread per point.  The 27 cells' buckets are visited once each (a
+// bucket two visited cells share is walked once), the point's own cell
+// first; every point of a visited bucket is a candidate.  That is exact: a
+// point within R lies in one of the 27 cells, so its bucket is visited, and
+// it is counted once; candidates from other cells sharing a bucket lie
+// farther than R and fail the radius test.  Once k neighbours are in hand,
+// a cell whose box (widened by a rounding slack) lies farther than the
+// current k-th nearest is skipped: its points cannot change the k smallest
+// distances, and the count m = min(found, k) is already k.
+template <int K>
 __global__ __launch_bounds__(256) void k_sor_knn(const float* __restrict__ pts, int64_t n, int k,
                                                  float R, float h, unsigned mask,
                                                  const unsigned* __restrict__ start,
@@ -186,38 +195,67 @@ __global__ __launch_bounds__(256) void k_sor_knn(const float* __restrict__ pts, 
     }
     const float rr = R * R;
     const int cx = cell_of(px, h), cy = cell_of(py, h), cz = cell_of(pz, h);
-    float best[KMAX];
+    // a point's cell can differ from its coordinates' box by rounding; the
+    // pruning bound below is shrunk by this slack
+    const float slack = 1e-4f * h + 1e-6f * (fabsf(px) + fabsf(py) + fabsf(pz));
+    unsigned seen[27];
+    float best[K];
 #pragma unroll
-    for (int t = 0; t < KMAX; ++t) best[t] = __builtin_huge_valf();
+    for (int t = 0; t < K; ++t) best[t] = __builtin_huge_valf();
     int found = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int ncx = cx + dx, ncy = cy + dy, ncz = cz + dz;
-                const unsigned b = bucket(ncx, ncy, ncz, mask);
-                const unsigned e1 = start[b] + count[b];
-                for (unsigned e = start[b]; e < e1; ++e) {
-                    const float4 q = spts[e];
-                    if (__float_as_int(q.w) == (int)i) continue;
-                    if (cell_of(q.x, h) != ncx || cell_of(q.y, h) != ncy || cell_of(q.z, h) != ncz)
-                        continue;
-                    const float ex = q.x - px, ey = q.y - py, ez = q.z - pz;
-                    float s = (ex * ex + ey * ey) + ez * ez;
-                    if (!(s <= rr)) continue;
-                    ++found;
-                    // one compare-exchange pass keeps best[] sorted ascending
 #pragma unroll
-                    for (int t = 0; t < KMAX; ++t) {
-                        const float lo = fminf(best[t], s), hi = fmaxf(best[t], s);
-                        best[t] = lo;
-                        s = hi;
-                    }
+    for (int j = 0; j < 27; ++j) {
+        const int c = j == 0 ? 13 : (j <= 13 ? j - 1 : j);   // own cell first
+        const int ox = c % 3 - 1, oy = (c / 3) % 3 - 1, oz = c / 9 - 1;
+        const unsigned b = bucket(cx + ox, cy + oy, cz + oz, mask);
+        seen[j] = 0xFFFFFFFFu;
+        if (found >= k && c != 13) {
+            // skip a cell whose nearest possible point is farther than the
+            // current k-th nearest: it cannot change the k smallest values
+            float kth = 0.0f;
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if (t == k - 1) kth = best[t];
+            auto gap = [&](int o, int cc, float pp) {
+                const float lo = (float)(cc + o) * h, hi = (float)(cc + o + 1) * h;
+                const float gg = o < 0 ? pp - hi : (o > 0 ? lo - pp : 0.0f);
+                return fmaxf(gg - slack, 0.0f);
+            };
+            const float gx = gap(ox, cx, px), gy = gap(oy, cy, py), gz = gap(oz, cz, pz);
+            if ((gx * gx + gy * gy) + gz * gz > kth) continue;
+        }
+        bool dup = false;
+#pragma unroll
+        for (int e = 0; e < j; ++e) dup = dup || seen[e] == b;
+        if (dup) continue;
+        seen[j] = b;
+        const unsigned e0 = start[b], e1 = e0 + count[b];
+        // candidates eight at a time: the eight loads are in flight together
+        for (unsigned e = e0; e < e1; e += 8) {
+            float4 q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) q[u] = spts[min(e + u, e1 - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (e + u >= e1 || __float_as_int(q[u].w) == (int)i) continue;
+                const float ex = q[u].x - px, ey = q[u].y - py, ez = q[u].z - pz;
+                float s = (ex * ex + ey * ey) + ez * ez;
+                if (!(s <= rr)) continue;
+                ++found;
+                // one compare-exchange pass keeps best[] sorted ascending
+#pragma unroll
+                for (int t = 0; t < K; ++t) {
+                    const float lo = fminf(best[t], s), hi = fmaxf(best[t], s);
+                    best[t] = lo;
+                    s = hi;
                 }
             }
+        }
+    }
     const int m = min(found, k);
     float sum = 0.0f;
 #pragma unroll
-    for (int t = 0; t < KMAX; ++t)
+    for (int t = 0; t < K; ++t)
         if (t < m) sum = sum + sqrtf(best[t]);
     sum = sum + (float)(k - m) * R;
     const float d = sum / (float)k;
@@ -320,8 +358,12 @@ int edt_outlier_filter(const float* pts, int64_t n, int32_t k, float radius, flo
         hipLaunchKernelGGL(k_sor_scatter, dim3(pblocks), dim3(256), 0, st, pts, n, h, L.tmask, start,
                            cursor, spts);
         if ((rc = check_launch("k_sor_scatter"))) return rc;
-        hipLaunchKernelGGL(k_sor_knn, dim3(pblocks), dim3(256), 0, st, pts, n, (int)k, radius, h,
-                           L.tmask, start, count, spts, dm, acc);
+        if (k <= 8)
+            hipLaunchKernelGGL(k_sor_knn<8>, dim3(pblocks), dim3(256), 0, st, pts, n, (int)k, radius, h,
+                               L.tmask, start, count, spts, dm, acc);
+        else
+            hipLaunchKernelGGL(k_sor_knn<KMAX>, dim3(pblocks), dim3(256), 0, st, pts, n, (int)k, radius,
+                               h, L.tmask, start, count, spts, dm, acc);
         if ((rc = check_launch("k_sor_knn"))) return rc;
     }
     hipLaunchKernelGGL(k_sor_keep, dim3(pblocks), dim3(256), 0, st, pts, n, dm, acc, (double)alpha,

@@ -95,7 +95,7 @@ def test_edge_cases():
     # far-apart points: nobody has a neighbour, every d_i is the radius
     far = (np.arange(30, dtype=np.float32)[:, None] * np.float32(0.5)) * np.ones((1, 3), np.float32)
     k, d, st = gpu_filter(far)
-    assert (d == np.float32(0.01)).all() and (k == 1).all() and st[1] == 0.0
+    assert (d == np.float32(0.01)).all() and (k == 1).all() and st[1] < 1e-7
 
 
 def test_filtered_frame_feeds_logodds_update():
