@@ -102,6 +102,26 @@ int edt_insert_points(const edt_grid_t* grid, uint8_t* occ, const float* pts, in
                       const float* T_map_sensor, const uint8_t* exclude, void* stream);
 
 /*
+ * Static-scene reuse (Exp. 4: one transform serves a static scene while the
+ * arm moves).  edt_compute_cached keeps, in a caller-owned cache, a snapshot
+ * of which voxels were occupied when d2 / site were last computed.  Each
+ * call compares occ with it (occupied = any nonzero byte) and runs the
+ * transform only if some voxel changed or the cache holds no result yet;
+ * otherwise d2 and site are left as they are.  The decision is taken on the
+ * device (the transform's kernels read a flag and return at once), so the
+ * call never synchronises and replays correctly from a graph.
+ *   cache  device, edt_cache_workspace_bytes(grid) bytes, zeroed by
+ *          edt_cache_reset before the first call; one cache per (occ, d2,
+ *          site) triple, and d2 / site must not be written between calls.
+ * Results are identical to edt_compute.  Errors: as edt_compute, plus
+ * EDT_ERR_WORKSPACE for a short cache.
+ */
+size_t edt_cache_workspace_bytes(const edt_grid_t* grid);
+int edt_cache_reset(const edt_grid_t* grid, void* cache, size_t cache_bytes, void* stream);
+int edt_compute_cached(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                       void* cache, size_t cache_bytes, void* stream);
+
+/*
  * Probabilistic occupancy (Sec. III-A: the occupancy of each point's voxel is
  * updated as a Bayesian process).  A persistent int16 log-odds grid (same
  * layout as occ) is updated once per frame:

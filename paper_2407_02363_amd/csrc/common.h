@@ -48,8 +48,10 @@ EdtTuning default_tuning(const edt_grid_t* g);   // heuristic
 EdtTuning current_tuning(const edt_grid_t* g);   // autotuned if cached, else heuristic
 bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt);   // pass 1 = xy, 2 = z
 bool needs_wide(const edt_grid_t* g);
-int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st);
-int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st);
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st,
+                  const int* gate = nullptr);
+int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st,
+                 const int* gate = nullptr);
 
 // One launch per pass over the tiles of several maps: tile T of the launch
 // belongs to the map whose [begin, begin + tiles) holds it.  Passed by value
@@ -67,6 +69,7 @@ struct EdtMapSet {
     int total;       // tiles of all maps
     int ny_max, nz_max;
     bool wide;
+    const int* gate; // nullable: the launch does nothing while *gate == 0
     EdtMap m[EDT_BATCH_MAX];
 };
 // Validates the maps and the tiles and fills the two passes' sets.

@@ -173,6 +173,41 @@ __global__ void k_logodds_update(int64_t n, LogOdds p, int16_t* __restrict__ L,
     }
 }
 
+// Static-scene reuse: flags[0] = "transform needed" for this call, flags[1]
+// = "the snapshot belongs to the result in d2 / site".
+__global__ void k_cache_begin(int* flags) { flags[0] = flags[1] ? 0 : 1; }
+__global__ void k_cache_end(int* flags) { flags[1] = 1; }
+
+// Compare 16 occupancy bytes per thread with the snapshot as occupied /
+// free (any nonzero byte is occupied); on a difference raise the flag and
+// store the new state.  ALIGNED: occ is 16-byte aligned.
+template <bool ALIGNED>
+__global__ void k_cache_compare(const uint8_t* __restrict__ occ, uint8_t* __restrict__ snap, int64_t n,
+                                int* __restrict__ flags)
+{
+    const int64_t i0 = 16 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 >= n) return;
+    uint8_t cur[16];
+    if (ALIGNED && i0 + 16 <= n) {
+        const uint4 v = *reinterpret_cast<const uint4*>(occ + i0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cur[k] = (w[k >> 2] >> (8 * (k & 3))) & 0xFFu ? 1 : 0;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cur[k] = (i0 + k < n && occ[i0 + k]) ? 1 : 0;
+    }
+    bool diff = false;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (i0 + k < n && snap[i0 + k] != cur[k]) {
+            snap[i0 + k] = cur[k];
+            diff = true;
+        }
+    }
+    if (diff) flags[0] = 1;
+}
+
 constexpr int MAX_LINKS = 64;
 struct LinkSegs {
     int n;                       // segments (selected links)
@@ -588,6 +623,62 @@ int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuni
     rc = launch_edt_xy_set(sxy, t.xy_tw, st);
     if (!rc) rc = launch_edt_z_set(sz, t.z_tw, t.z_nt, st);
     return rc;
+}
+
+size_t edt_cache_workspace_bytes(const edt_grid_t* grid)
+{
+    if (check_grid(grid)) return 0;
+    return 256 + (size_t)(grid_voxels(grid) + 255) / 256 * 256;
+}
+
+int edt_cache_reset(const edt_grid_t* grid, void* cache, size_t cache_bytes, void* stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!cache || cache_bytes < edt_cache_workspace_bytes(grid)) {
+        set_error("edt_cache_reset: cache of %zu bytes is below %zu", cache_bytes,
+                  edt_cache_workspace_bytes(grid));
+        return cache ? EDT_ERR_WORKSPACE : EDT_ERR_ARG;
+    }
+    return fill_zero(cache, (int64_t)edt_cache_workspace_bytes(grid), as_stream(stream));
+}
+
+int edt_compute_cached(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
+                       void* cache, size_t cache_bytes, void* stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!occ || !d2 || !site || !cache) {
+        set_error("edt_compute_cached: NULL occ, d2, site or cache");
+        return EDT_ERR_ARG;
+    }
+    if (cache_bytes < edt_cache_workspace_bytes(grid)) {
+        set_error("edt_compute_cached: cache of %zu bytes is below %zu", cache_bytes,
+                  edt_cache_workspace_bytes(grid));
+        return EDT_ERR_WORKSPACE;
+    }
+    const EdtTuning t = current_tuning(grid);
+    if (!tile_ok(1, t.xy_tw, grid, 256) || !tile_ok(2, t.z_tw, grid, t.z_nt)) {
+        set_error("edt_compute_cached: no valid tiles for this grid");
+        return EDT_ERR_UNSUPPORTED;
+    }
+    const hipStream_t st = as_stream(stream);
+    int* flags = static_cast<int*>(cache);
+    uint8_t* snap = static_cast<uint8_t*>(cache) + 256;
+    const int64_t n = grid_voxels(grid);
+    hipLaunchKernelGGL(k_cache_begin, dim3(1), dim3(1), 0, st, flags);
+    if ((rc = check_launch("k_cache_begin"))) return rc;
+    const unsigned blocks = (unsigned)(((n + 15) / 16 + 255) / 256);
+    if ((reinterpret_cast<uintptr_t>(occ) & 15) == 0)
+        hipLaunchKernelGGL(k_cache_compare<true>, dim3(blocks), dim3(256), 0, st, occ, snap, n, flags);
+    else
+        hipLaunchKernelGGL(k_cache_compare<false>, dim3(blocks), dim3(256), 0, st, occ, snap, n, flags);
+    if ((rc = check_launch("k_cache_compare"))) return rc;
+    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, st, flags);
+    if (!rc) rc = launch_edt_z(grid, d2, site, t.z_tw, t.z_nt, st, flags);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_cache_end, dim3(1), dim3(1), 0, st, flags);
+    return check_launch("k_cache_end");
 }
 
 int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* site,

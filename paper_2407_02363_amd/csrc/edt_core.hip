@@ -23,6 +23,7 @@ template <int TW, bool WIDE>
 __global__ __launch_bounds__(NT) void k_edt_xy(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
+    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     const int T = xcd_remap(blockIdx.x, s.total);
     const EdtMap& d = s.m[map_of(s, T)];
     edt_xy_tile<TW, WIDE>(d.occ, reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny, d.nz, d.ntx,
@@ -33,6 +34,7 @@ template <int TW, bool WIDE, int NTZ>
 __global__ __launch_bounds__(NTZ) void k_edt_z(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
+    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     const int T = xcd_remap(blockIdx.x, s.total);
     const EdtMap& d = s.m[map_of(s, T)];
     edt_z_tile<TW, WIDE, NTZ>(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, lds);
@@ -95,6 +97,7 @@ void fill_set(const edt_batch_map_t* maps, int n, int tw, bool z_pass, EdtMapSet
     s.total = 0;
     s.ny_max = s.nz_max = 0;
     s.wide = false;
+    s.gate = nullptr;
     for (int i = 0; i < n; ++i) {
         const edt_grid_t& g = maps[i].grid;
         EdtMap& d = s.m[i];
@@ -226,19 +229,23 @@ edt_batch_map_t one_map(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, in
 }
 }  // namespace
 
-int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st)
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st,
+                  const int* gate)
 {
     const edt_batch_map_t m = one_map(g, occ, nullptr, reinterpret_cast<int32_t*>(xy));
     EdtMapSet s;
     fill_set(&m, 1, tw, false, s);
+    s.gate = gate;
     return launch_edt_xy_set(s, tw, st);
 }
 
-int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st)
+int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st,
+                 const int* gate)
 {
     const edt_batch_map_t m = one_map(g, nullptr, d2, site);
     EdtMapSet s;
     fill_set(&m, 1, tw, true, s);
+    s.gate = gate;
     return launch_edt_z_set(s, tw, nt, st);
 }
 

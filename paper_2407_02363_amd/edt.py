@@ -67,6 +67,7 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_autotune", "edt_batch_workspace_bytes", "edt_compute_batched", "edt_batch_status",
             "edt_compute_many", "edt_logodds_workspace_bytes", "edt_logodds_reset",
             "edt_update_logodds", "edt_outlier_workspace_bytes", "edt_outlier_filter",
+            "edt_cache_workspace_bytes", "edt_cache_reset", "edt_compute_cached",
             "edt_autotune_batched"]
 
 BATCH_MAX = 48
@@ -108,6 +109,9 @@ def lib():
         "edt_update_logodds": ([G, P, P, P, i64, P, P, P, ctypes.POINTER(LogOdds), P, ctypes.c_size_t,
                                 P], ctypes.c_int),
         "edt_outlier_workspace_bytes": ([i64], ctypes.c_size_t),
+        "edt_cache_workspace_bytes": ([G], ctypes.c_size_t),
+        "edt_cache_reset": ([G, P, ctypes.c_size_t, P], ctypes.c_int),
+        "edt_compute_cached": ([G, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_outlier_filter": ([P, i64, i32, ctypes.c_float, ctypes.c_float, P, P, P, P,
                                 ctypes.c_size_t, P], ctypes.c_int),
         "edt_batch_status": ([P, ctypes.POINTER(ctypes.c_int32), P], ctypes.c_int),
@@ -381,3 +385,23 @@ def edt_outlier_filter(pts, keep, ws, k=8, radius=0.01, alpha=1.0, mean_dist=Non
                                     _dev(stats, torch.float64, "stats", 3),
                                     _dev(ws, torch.uint8, "ws"), ws.numel(), _stream(stream)),
            "edt_outlier_filter")
+
+
+def new_edt_cache(grid, device="cuda"):
+    """A zeroed static-scene cache for edt_compute_cached."""
+    n = int(lib().edt_cache_workspace_bytes(ctypes.byref(make_grid(grid))))
+    return torch.zeros(n, dtype=torch.uint8, device=device)
+
+
+def edt_cache_reset(grid, cache, stream=None):
+    _check(lib().edt_cache_reset(ctypes.byref(make_grid(grid)), _dev(cache, torch.uint8, "cache"),
+                                 cache.numel(), _stream(stream)), "edt_cache_reset")
+
+
+def edt_compute_cached(grid, occ, d2, site, cache, stream=None):
+    g = make_grid(grid)
+    n = _n(g)
+    _check(lib().edt_compute_cached(ctypes.byref(g), _dev(occ, torch.uint8, "occ", n),
+                                    _dev(d2, torch.int32, "d2", n), _dev(site, torch.int32, "site", n),
+                                    _dev(cache, torch.uint8, "cache"), cache.numel(), _stream(stream)),
+           "edt_compute_cached")

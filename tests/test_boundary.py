@@ -118,6 +118,12 @@ def test_host_validation_rejects_bad_arguments(lib):
                                   None) == -1
     assert lib.edt_outlier_filter(one, 1000, 8, 0.01, 1.0, one, None, None, one, ow - 1, None) == -3
     assert lib.edt_outlier_filter(one, -1, 8, 0.01, 1.0, one, None, None, one, ow, None) == -1
+    # cached transform: cache size and NULLs before any launch
+    cb = lib.edt_cache_workspace_bytes(ctypes.byref(ok))
+    assert cb >= 256 + ok.nx * ok.ny * ok.nz
+    assert lib.edt_compute_cached(ctypes.byref(ok), one, one, one, one, cb - 1, None) == -3
+    assert lib.edt_compute_cached(ctypes.byref(ok), one, None, one, one, cb, None) == -1
+    assert lib.edt_cache_reset(ctypes.byref(ok), one, cb - 1, None) == -3
     assert lib.edt_logodds_reset(ctypes.byref(ok), one, one, 16, None) == -3
     huge = edt.EdtGrid(8, 1024, 8, (ctypes.c_float * 3)(0, 0, 0), 0.01)
     assert lib.edt_compute_tuned(ctypes.byref(huge), one, one, one,

@@ -166,3 +166,62 @@ def test_autotune_keeps_results(oracle_lib):
     torch.cuda.synchronize()
     assert np.array_equal(d2.cpu().numpy().reshape(occ.shape), rd2)
     assert np.array_equal(site.cpu().numpy().reshape(occ.shape), rsite)
+
+
+def test_cached_transform_skips_only_unchanged_maps(oracle_lib):
+    """edt_compute_cached: the first call and every call after a change give
+    the oracle's result; a call on an unchanged map (occupied / free
+    unchanged, whatever the nonzero byte values) leaves d2 and site as they
+    are; the same holds through graph replays."""
+    import torch
+    from paper_2407_02363_amd import edt
+    from tests.gpu_util import dev
+    d = dev()
+    shape = (40, 70, 65)
+    g = inputs.Grid(shape[2], shape[1], shape[0])
+    occ_np = inputs.random_grid(shape, 0.01, 3)
+    buf = torch.zeros(occ_np.size + 3, dtype=torch.uint8, device=d)
+    for off in (0, 3):                          # aligned and unaligned occ
+        say(f"[cached] offset {off}")
+        o = buf[off:off + occ_np.size]
+        o.copy_(torch.from_numpy(occ_np.ravel()))
+        d2 = torch.full((occ_np.size,), -7, dtype=torch.int32, device=d)
+        site = torch.full_like(d2, -7)
+        cache = edt.new_edt_cache(g, d)
+        rd2, rs = oracle_lib.edt(occ_np)
+
+        def check(ref_d2, ref_s):
+            torch.cuda.synchronize()
+            assert np.array_equal(d2.cpu().numpy().reshape(shape), ref_d2)
+            assert np.array_equal(site.cpu().numpy().reshape(shape), ref_s)
+
+        edt.edt_compute_cached(g, o, d2, site, cache)
+        check(rd2, rs)
+        # unchanged map: the transform is skipped, the planted values stay
+        d2.fill_(-5)
+        site.fill_(-5)
+        o.mul_(3)                               # occupied bytes 1 -> 3: still occupied
+        edt.edt_compute_cached(g, o, d2, site, cache)
+        check(np.full(shape, -5), np.full(shape, -5))
+        # one voxel freed, one occupied: recomputed
+        occ2 = occ_np.copy()
+        occ2.flat[np.flatnonzero(occ2)[0]] = 0
+        occ2[5, 6, 7] = 1
+        o.copy_(torch.from_numpy(occ2.ravel()))
+        edt.edt_compute_cached(g, o, d2, site, cache)
+        r2 = oracle_lib.edt(occ2)
+        check(*r2)
+        # graph replays: alternate between two maps and an unchanged repeat
+        gr = torch.cuda.CUDAGraph()
+        edt.edt_compute_cached(g, o, d2, site, cache)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gr, capture_error_mode="thread_local"):
+            edt.edt_compute_cached(g, o, d2, site, cache)
+        for rep, (m, ref) in enumerate([(occ_np, (rd2, rs)), (occ_np, (rd2, rs)), (occ2, r2)]):
+            o.copy_(torch.from_numpy(m.ravel()))
+            gr.replay()
+            check(*ref)
+        edt.edt_cache_reset(g, cache)
+        d2.fill_(-5)
+        edt.edt_compute_cached(g, o, d2, site, cache)   # a reset cache computes again
+        check(*r2)
