@@ -247,14 +247,18 @@ int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t
  * band queries its own positions.  xy_tile is one of 16, 32, 64; z_tile one
  * of 8, 16, 32, 64; a tile whose work-group would need more local memory
  * than the device has is rejected with EDT_ERR_UNSUPPORTED.  Results do
- * not depend on the tiles.  The xy work-groups have 256 threads; the z
- * work-group size is z_group.
+ * not depend on the tiles.  The work-group sizes are xy_group and
+ * z_group.
  */
 typedef struct edt_tuning_t {
     int32_t xy_tile;
     int32_t z_tile;
     int32_t z_group;   /* threads per z work-group: 64, 128 or 256 (0 = 256);
                           z_tile <= z_group, bands per column = z_group / z_tile */
+    int32_t xy_group;  /* threads per xy work-group: 64, 128 or 256 (0 = 256);
+                          xy_tile <= xy_group, bands per column = xy_group / xy_tile.
+                          xy_tile = xy_group and z_tile = z_group give one band per
+                          line in both passes, the paper's naive m1 = m2 = m3 = 1 */
 } edt_tuning_t;
 
 /* Tiles edt_compute uses for this grid: the autotuner's choice if
@@ -345,7 +349,7 @@ size_t edt_batch_workspace_bytes(int32_t n_maps);
  *           zeroed by the call itself (a fill kernel, no memset node); two
  *           batches in flight at once need two workspaces.
  *   tuning  NULL = the batch autotuner's choice for this shape class, else
- *           xy_tile in {16, 32}, z_tile in {16, 32, 64} (z_group is ignored:
+ *           xy_tile in {16, 32}, z_tile in {16, 32, 64} (z_group, xy_group ignored:
  *           batches use 256-thread work-groups).
  * Errors: EDT_ERR_UNSUPPORTED for an axis above 512 or tiles that do not
  * fit; argument errors as for edt_compute.

@@ -13,6 +13,7 @@ Functions (each cites the paper passage it follows in its docstring):
   update_logodds(...)   per-frame Bayesian occupancy update (Sec. III-A)
   ray_walk(a, b)        voxels a sensor ray crosses (the update's traversal)
   outlier_filter(...)   statistical outlier filtering of a cloud (Sec. III-A)
+  jfa(occ)              jump flooding, the approximate transform of Table 2
 """
 from __future__ import annotations
 
@@ -72,6 +73,8 @@ def _load():
         lib.oracle_outlier_mean_dist.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int,
                                                  ctypes.c_float, P]
         lib.oracle_outlier_mean_dist.restype = None
+        lib.oracle_jfa.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        lib.oracle_jfa.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -211,3 +214,16 @@ def outlier_mean_dist(pts: np.ndarray, idx: np.ndarray, k: int = 8, radius: floa
     _load().oracle_outlier_mean_dist(_ptr(pts), pts.shape[0], _ptr(idx), idx.size, int(k),
                                      float(radius), _ptr(out))
     return out
+
+
+def jfa(occ: np.ndarray):
+    """Jump flooding (the approximate transform compared in Table 2): (d2,
+    site) like edt(), but each voxel's site is only the best the flooding
+    found."""
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    nz, ny, nx = occ.shape
+    d2 = np.empty(occ.shape, np.int32)
+    site = np.empty(occ.shape, np.int32)
+    if _load().oracle_jfa(_ptr(occ), nx, ny, nz, _ptr(d2), _ptr(site)) != 0:
+        raise RuntimeError("oracle_jfa failed")
+    return d2, site

@@ -567,3 +567,68 @@ void oracle_outlier_filter(const float* pts, int64_t n, int k, float R, double a
     stats[1] = sigma;
     stats[2] = thr;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Jump flooding (the JFA of the paper's EDT comparison, Sec. IV / Table 2):*/
+/* an approximate transform.  Seeds are the occupied voxels (site = own     */
+/* index).  For step k = S/2, S/4, ..., 1 (S the smallest power of two      */
+/* >= the largest axis), every voxel looks at the sites held by itself and  */
+/* the 26 voxels at offsets in {-k, 0, k}^3 that lie in the grid, and keeps */
+/* the one closest to it (squared voxel distance; the smaller linear index  */
+/* on ties); all voxels read the previous step's sites.  d2 is the squared  */
+/* distance to the final site (INT32_MAX / -1 where none was found).        */
+/* ------------------------------------------------------------------------ */
+int oracle_jfa(const uint8_t* occ, int nx, int ny, int nz, int32_t* d2, int32_t* site)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    int32_t* cur = (int32_t*)malloc((size_t)n * 4);
+    int32_t* nxt = (int32_t*)malloc((size_t)n * 4);
+    if (!cur || !nxt) { free(cur); free(nxt); return -1; }
+    for (int64_t v = 0; v < n; ++v) cur[v] = occ[v] ? (int32_t)v : -1;
+    int S = 1;
+    while (S < nx || S < ny || S < nz) S <<= 1;
+    for (int k = S / 2; k >= 1; k /= 2) {
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    int32_t best = -1;
+                    int64_t bd = 0;
+                    for (int oz = -1; oz <= 1; ++oz)
+                        for (int oy = -1; oy <= 1; ++oy)
+                            for (int ox = -1; ox <= 1; ++ox) {
+                                const int qx = x + ox * k, qy = y + oy * k, qz = z + oz * k;
+                                if (qx < 0 || qx >= nx || qy < 0 || qy >= ny || qz < 0 || qz >= nz)
+                                    continue;
+                                const int32_t s = cur[qx + (int64_t)nx * (qy + (int64_t)ny * qz)];
+                                if (s < 0) continue;
+                                const int sx = s % nx, sy = (s / nx) % ny, sz = s / (nx * ny);
+                                const int64_t dd = (int64_t)(sx - x) * (sx - x) +
+                                                   (int64_t)(sy - y) * (sy - y) +
+                                                   (int64_t)(sz - z) * (sz - z);
+                                if (best < 0 || dd < bd || (dd == bd && s < best)) {
+                                    best = s;
+                                    bd = dd;
+                                }
+                            }
+                    nxt[x + (int64_t)nx * (y + (int64_t)ny * z)] = best;
+                }
+        int32_t* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t s = cur[v];
+        site[v] = s;
+        if (s < 0) {
+            d2[v] = INT32_MAX;
+            continue;
+        }
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+        const int sx = s % nx, sy = (s / nx) % ny, sz = s / (nx * ny);
+        d2[v] = (sx - x) * (sx - x) + (sy - y) * (sy - y) + (sz - z) * (sz - z);
+    }
+    free(cur);
+    free(nxt);
+    return 0;
+}

@@ -243,6 +243,7 @@ int batch_common(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t w
         t.xy_tw = tuning->xy_tile;
         t.z_tw = tuning->z_tile;
         t.z_nt = 256;
+        t.xy_nt = 256;
     } else {
         t = batch_current(n_maps, nx, ny, nz);
     }
@@ -350,7 +351,7 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
             if (rc) break;
             if (total / reps < best_ms) {
                 best_ms = total / reps;
-                bt = EdtTuning{txy, tz, 256};
+                bt = EdtTuning{txy, tz, 256, 256};
             }
         }
         if (rc) break;
@@ -376,6 +377,7 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
         best->xy_tile = bt.xy_tw;
         best->z_tile = bt.z_tw;
         best->z_group = 256;
+        best->xy_group = 256;
     }
     if (best_us) *best_us = 1000.0f * best_ms;
     // leave the chosen tiling's result in the outputs

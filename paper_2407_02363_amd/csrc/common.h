@@ -43,13 +43,24 @@ struct EdtTuning {
     int xy_tw;
     int z_tw;
     int z_nt;   // threads per z work-group (64, 128 or 256)
+    int xy_nt;  // threads per xy work-group (64, 128 or 256)
 };
+// The tiles an API tuning struct asks for (0 group sizes mean 256).
+inline EdtTuning tuning_from(const edt_tuning_t* p)
+{
+    EdtTuning t;
+    t.xy_tw = p->xy_tile;
+    t.z_tw = p->z_tile;
+    t.z_nt = p->z_group ? p->z_group : 256;
+    t.xy_nt = p->xy_group ? p->xy_group : 256;
+    return t;
+}
 EdtTuning default_tuning(const edt_grid_t* g);   // heuristic
 EdtTuning current_tuning(const edt_grid_t* g);   // autotuned if cached, else heuristic
 bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt);   // pass 1 = xy, 2 = z
 bool needs_wide(const edt_grid_t* g);
-int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st,
-                  const int* gate = nullptr);
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, int nt,
+                  hipStream_t st, const int* gate = nullptr);
 int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st,
                  const int* gate = nullptr);
 
@@ -75,7 +86,7 @@ struct EdtMapSet {
 // Validates the maps and the tiles and fills the two passes' sets.
 int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMapSet& xy,
                   EdtMapSet& z);
-int launch_edt_xy_set(const EdtMapSet& s, int tw, hipStream_t st);
+int launch_edt_xy_set(const EdtMapSet& s, int tw, int nt, hipStream_t st);
 int launch_edt_z_set(const EdtMapSet& s, int tw, int nt, hipStream_t st);
 
 // Work-group index remap so that consecutive logical tiles land on the same

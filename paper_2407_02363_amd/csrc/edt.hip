@@ -558,22 +558,15 @@ int edt_compute_stage(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, i
         set_error("edt_compute: NULL occ, d2 or site");
         return EDT_ERR_ARG;
     }
-    EdtTuning t;
-    if (tuning) {
-        t.xy_tw = tuning->xy_tile;
-        t.z_tw = tuning->z_tile;
-        t.z_nt = tuning->z_group ? tuning->z_group : 256;
-    } else {
-        t = current_tuning(grid);
-    }
-    if (!tile_ok(1, t.xy_tw, grid, 256) || !tile_ok(2, t.z_tw, grid, t.z_nt)) {
-        set_error("tiles (%d, %d / %d) not valid for a %d x %d x %d grid", t.xy_tw, t.z_tw, t.z_nt,
-                  grid->nx, grid->ny, grid->nz);
+    const EdtTuning t = tuning ? tuning_from(tuning) : current_tuning(grid);
+    if (!tile_ok(1, t.xy_tw, grid, t.xy_nt) || !tile_ok(2, t.z_tw, grid, t.z_nt)) {
+        set_error("tiles (%d / %d, %d / %d) not valid for a %d x %d x %d grid", t.xy_tw, t.xy_nt,
+                  t.z_tw, t.z_nt, grid->nx, grid->ny, grid->nz);
         return EDT_ERR_UNSUPPORTED;
     }
     const hipStream_t st = as_stream(stream);
     if (stage & EDT_STAGE_XY) {
-        rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, st);
+        rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, t.xy_nt, st);
         if (rc) return rc;
     }
     if (stage & EDT_STAGE_Z) rc = launch_edt_z(grid, d2, site, t.z_tw, t.z_nt, st);
@@ -603,9 +596,7 @@ int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuni
     }
     EdtTuning t;
     if (tuning) {
-        t.xy_tw = tuning->xy_tile;
-        t.z_tw = tuning->z_tile;
-        t.z_nt = tuning->z_group ? tuning->z_group : 256;
+        t = tuning_from(tuning);
     } else {
         edt_grid_t big = maps[0].grid;
         for (int i = 1; i < n_maps; ++i) {
@@ -620,7 +611,7 @@ int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuni
     int rc = make_map_sets(maps, n_maps, t, sxy, sz);
     if (rc) return rc;
     const hipStream_t st = as_stream(stream);
-    rc = launch_edt_xy_set(sxy, t.xy_tw, st);
+    rc = launch_edt_xy_set(sxy, t.xy_tw, t.xy_nt, st);
     if (!rc) rc = launch_edt_z_set(sz, t.z_tw, t.z_nt, st);
     return rc;
 }
@@ -658,7 +649,7 @@ int edt_compute_cached(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, 
         return EDT_ERR_WORKSPACE;
     }
     const EdtTuning t = current_tuning(grid);
-    if (!tile_ok(1, t.xy_tw, grid, 256) || !tile_ok(2, t.z_tw, grid, t.z_nt)) {
+    if (!tile_ok(1, t.xy_tw, grid, t.xy_nt) || !tile_ok(2, t.z_tw, grid, t.z_nt)) {
         set_error("edt_compute_cached: no valid tiles for this grid");
         return EDT_ERR_UNSUPPORTED;
     }
@@ -674,7 +665,7 @@ int edt_compute_cached(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, 
     else
         hipLaunchKernelGGL(k_cache_compare<false>, dim3(blocks), dim3(256), 0, st, occ, snap, n, flags);
     if ((rc = check_launch("k_cache_compare"))) return rc;
-    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, st, flags);
+    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, t.xy_nt, st, flags);
     if (!rc) rc = launch_edt_z(grid, d2, site, t.z_tw, t.z_nt, st, flags);
     if (rc) return rc;
     hipLaunchKernelGGL(k_cache_end, dim3(1), dim3(1), 0, st, flags);

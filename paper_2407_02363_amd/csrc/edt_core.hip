@@ -19,15 +19,15 @@ __device__ __forceinline__ int map_of(const EdtMapSet& s, int T)
     return __builtin_amdgcn_readfirstlane(m);
 }
 
-template <int TW, bool WIDE>
-__global__ __launch_bounds__(NT) void k_edt_xy(EdtMapSet s)
+template <int TW, bool WIDE, int NTX>
+__global__ __launch_bounds__(NTX) void k_edt_xy(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
     if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     const int T = xcd_remap(blockIdx.x, s.total);
     const EdtMap& d = s.m[map_of(s, T)];
-    edt_xy_tile<TW, WIDE>(d.occ, reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny, d.nz, d.ntx,
-                          T - d.begin, lds);
+    edt_xy_tile<TW, WIDE, NTX>(d.occ, reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny, d.nz, d.ntx,
+                               T - d.begin, lds);
 }
 
 template <int TW, bool WIDE, int NTZ>
@@ -56,20 +56,21 @@ int allow_lds(K kernel, bool& done)
     return EDT_OK;
 }
 
-template <int TW, bool WIDE>
+template <int TW, bool WIDE, int NTX>
 int launch_xy_w(const EdtMapSet& s, hipStream_t st)
 {
     static bool done = false;
-    int rc = allow_lds(k_edt_xy<TW, WIDE>, done);
+    int rc = allow_lds(k_edt_xy<TW, WIDE, NTX>, done);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_edt_xy<TW, WIDE>), dim3(s.total), dim3(NT), xy_lds(TW, s.ny_max), st, s);
+    hipLaunchKernelGGL((k_edt_xy<TW, WIDE, NTX>), dim3(s.total), dim3(NTX), xy_lds(TW, s.ny_max, NTX),
+                       st, s);
     return check_launch("k_edt_xy");
 }
 
-template <int TW>
+template <int TW, int NTX>
 int launch_xy_tw(const EdtMapSet& s, hipStream_t st)
 {
-    return s.wide ? launch_xy_w<TW, true>(s, st) : launch_xy_w<TW, false>(s, st);
+    return s.wide ? launch_xy_w<TW, true, NTX>(s, st) : launch_xy_w<TW, false, NTX>(s, st);
 }
 
 template <int TW, bool WIDE, int NTZ>
@@ -127,7 +128,9 @@ bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt)
     constexpr size_t LDS_MAX = 160 * 1024 - 8192;
     if (pass == 1) {
         if (tw != 16 && tw != 32 && tw != 64) return false;
-        return xy_lds(tw, g->ny) <= LDS_MAX;
+        if (nt != 64 && nt != 128 && nt != 256) return false;
+        if (tw > nt) return false;
+        return xy_lds(tw, g->ny, nt) <= LDS_MAX;
     }
     if (tw != 8 && tw != 16 && tw != 32 && tw != 64) return false;
     if (nt != 64 && nt != 128 && nt != 256) return false;
@@ -143,6 +146,7 @@ EdtTuning default_tuning(const edt_grid_t* g)
     t.xy_tw = g->ny <= 256 ? 32 : 16;
     t.z_tw = g->nz <= 128 ? 64 : (g->nz <= 256 ? 32 : 16);
     t.z_nt = 256;
+    t.xy_nt = 256;
     if (!tile_ok(1, t.xy_tw, g, 256)) t.xy_tw = 16;
     if (!tile_ok(2, t.z_tw, g, t.z_nt)) t.z_tw = 8;
     return t;
@@ -169,9 +173,9 @@ int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMap
         big.ny = std::max(big.ny, g->ny);
         big.nz = std::max(big.nz, g->nz);
     }
-    if (!tile_ok(1, t.xy_tw, &big, 256) || !tile_ok(2, t.z_tw, &big, t.z_nt)) {
-        set_error("tiles (%d, %d / %d) not valid for maps up to %d x %d x %d", t.xy_tw, t.z_tw, t.z_nt,
-                  big.nx, big.ny, big.nz);
+    if (!tile_ok(1, t.xy_tw, &big, t.xy_nt) || !tile_ok(2, t.z_tw, &big, t.z_nt)) {
+        set_error("tiles (%d / %d, %d / %d) not valid for maps up to %d x %d x %d", t.xy_tw, t.xy_nt,
+                  t.z_tw, t.z_nt, big.nx, big.ny, big.nz);
         return EDT_ERR_UNSUPPORTED;
     }
     fill_set(maps, n, t.xy_tw, false, xy);
@@ -179,14 +183,29 @@ int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMap
     return EDT_OK;
 }
 
-int launch_edt_xy_set(const EdtMapSet& s, int tw, hipStream_t st)
+int launch_edt_xy_set(const EdtMapSet& s, int tw, int nt, hipStream_t st)
 {
-    switch (tw) {
-        case 64: return launch_xy_tw<64>(s, st);
-        case 32: return launch_xy_tw<32>(s, st);
-        case 16: return launch_xy_tw<16>(s, st);
-        default: set_error("bad xy tile width %d", tw); return EDT_ERR_ARG;
+    if (nt == 256) {
+        switch (tw) {
+            case 64: return launch_xy_tw<64, 256>(s, st);
+            case 32: return launch_xy_tw<32, 256>(s, st);
+            case 16: return launch_xy_tw<16, 256>(s, st);
+        }
+    } else if (nt == 128) {
+        switch (tw) {
+            case 64: return launch_xy_tw<64, 128>(s, st);
+            case 32: return launch_xy_tw<32, 128>(s, st);
+            case 16: return launch_xy_tw<16, 128>(s, st);
+        }
+    } else if (nt == 64) {
+        switch (tw) {
+            case 64: return launch_xy_tw<64, 64>(s, st);
+            case 32: return launch_xy_tw<32, 64>(s, st);
+            case 16: return launch_xy_tw<16, 64>(s, st);
+        }
     }
+    set_error("bad xy tile %d / group %d", tw, nt);
+    return EDT_ERR_ARG;
 }
 
 int launch_edt_z_set(const EdtMapSet& s, int tw, int nt, hipStream_t st)
@@ -229,14 +248,14 @@ edt_batch_map_t one_map(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, in
 }
 }  // namespace
 
-int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, hipStream_t st,
-                  const int* gate)
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, int nt,
+                  hipStream_t st, const int* gate)
 {
     const edt_batch_map_t m = one_map(g, occ, nullptr, reinterpret_cast<int32_t*>(xy));
     EdtMapSet s;
     fill_set(&m, 1, tw, false, s);
     s.gate = gate;
-    return launch_edt_xy_set(s, tw, st);
+    return launch_edt_xy_set(s, tw, nt, st);
 }
 
 int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st,

@@ -396,19 +396,19 @@ __host__ __device__ inline size_t z_lds(int tw, int nzv, int nt = NT)
     return (size_t)4 * nt * ((nzv + nt / tw - 1) / (nt / tw));
 }
 
-__host__ __device__ inline size_t xy_lds(int tw, int nyv)
+__host__ __device__ inline size_t xy_lds(int tw, int nyv, int nt = NT)
 {
-    const size_t ent = (size_t)4 * NT * ((nyv + NT / tw - 1) / (NT / tw));
+    const size_t ent = (size_t)4 * nt * ((nyv + nt / tw - 1) / (nt / tw));
     return (ent > 8 * (size_t)XSTAGE_WORDS ? ent : 8 * (size_t)XSTAGE_WORDS) + 12 * (size_t)nyv;
 }
 
 // One xy tile: slice z, columns [x0, x0 + TW), T = z * ntx + x0 / TW.
-template <int TW, bool WIDE>
+template <int TW, bool WIDE, int NTX = NT>
 __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
                                             uint32_t* __restrict__ xy, int nx, int ny, int nz,
                                             int ntx, int T, uint32_t* lds)
 {
-    constexpr int NB = NT / TW;
+    constexpr int NB = NTX / TW;
     constexpr int XCH = 8;   // 16-byte loads in flight per thread
     const int L = (ny + NB - 1) / NB;
     // step 1 stages rows in the envelope area, which is only written after it
@@ -452,19 +452,19 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
             const long long c0 = (fs + mis) >> 4;
             const int off = (int)((fs + mis) & 15);
             const int nch = (int)(((fs + (long long)rows * nx - 1 + mis) >> 4) - c0 + 1);
-            for (int i0 = 0; i0 < nch; i0 += NT * XCH) {
+            for (int i0 = 0; i0 < nch; i0 += NTX * XCH) {
                 uint4 v[XCH];
                 if (any_whole) {
 #pragma unroll
                     for (int u = 0; u < XCH; ++u) {
-                        long long k = c0 + min(i0 + u * NT + (int)threadIdx.x, nch - 1);
+                        long long k = c0 + min(i0 + u * NTX + (int)threadIdx.x, nch - 1);
                         k = k < kf ? kf : (k >= ke ? ke - 1 : k);
                         v[u] = base16[k];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < XCH; ++u) {
-                    const int i = i0 + u * NT + (int)threadIdx.x;
+                    const int i = i0 + u * NTX + (int)threadIdx.x;
                     if (i < nch) {
                         const long long k = c0 + i;
                         uint32_t m = 0;
@@ -482,7 +482,7 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
                 }
             }
             __syncthreads();
-            for (int r = threadIdx.x; r < rows; r += NT) {
+            for (int r = threadIdx.x; r < rows; r += NTX) {
                 const int rb = off + r * nx;
                 // columns [64c, 64c + 64) of row r, bits past the row end cleared
                 auto word = [&](int c) -> uint64_t {

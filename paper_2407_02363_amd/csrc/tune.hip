@@ -30,15 +30,16 @@ int time_pass(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, int32_t* sit
         return EDT_ERR_HIP;
     }
     int rc = EDT_OK;
-    const int xy_prep = current_tuning(g).xy_tw;
+    const EdtTuning prep = current_tuning(g);
     float total = 0.0f;
     // iteration 0 is an untimed warm-up
     for (int r = 0; r <= reps && !rc; ++r) {
         // the z pass consumes its input in place: give it a fresh xy result
-        if (pass == 2) rc = launch_edt_xy(g, occ, reinterpret_cast<uint32_t*>(site), xy_prep, st);
+        if (pass == 2)
+            rc = launch_edt_xy(g, occ, reinterpret_cast<uint32_t*>(site), prep.xy_tw, prep.xy_nt, st);
         if (rc) break;
         (void)hipEventRecord(a, st);
-        rc = pass == 1 ? launch_edt_xy(g, occ, reinterpret_cast<uint32_t*>(site), tw, st)
+        rc = pass == 1 ? launch_edt_xy(g, occ, reinterpret_cast<uint32_t*>(site), tw, nt, st)
                        : launch_edt_z(g, d2, site, tw, nt, st);
         (void)hipEventRecord(b, st);
         if (rc) break;
@@ -83,6 +84,7 @@ int edt_default_tuning(const edt_grid_t* grid, edt_tuning_t* out)
     out->xy_tile = t.xy_tw;
     out->z_tile = t.z_tw;
     out->z_group = t.z_nt;
+    out->xy_group = t.xy_nt;
     return EDT_OK;
 }
 
@@ -120,10 +122,10 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz, bnt};
+        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz, bnt, 256};
     }
     // leave a complete transform in d2 / site
-    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), bxy, st);
+    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), bxy, 256, st);
     if (!rc) rc = launch_edt_z(grid, d2, site, bz, bnt, st);
     if (rc) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) {
@@ -134,6 +136,7 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
         best->xy_tile = bxy;
         best->z_tile = bz;
         best->z_group = bnt;
+        best->xy_group = 256;
     }
     if (best_us) *best_us = 1000.0f * (best_xy + best_z);
     return EDT_OK;

@@ -41,7 +41,8 @@ class SphereResult(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("xy_tile", ctypes.c_int32), ("z_tile", ctypes.c_int32), ("z_group", ctypes.c_int32)]
+    _fields_ = [("xy_tile", ctypes.c_int32), ("z_tile", ctypes.c_int32), ("z_group", ctypes.c_int32),
+                ("xy_group", ctypes.c_int32)]
 
 
 class LogOdds(ctypes.Structure):
@@ -218,7 +219,8 @@ def _tuning(t):
         return None
     if isinstance(t, Tuning):
         return ctypes.byref(t)
-    return ctypes.byref(Tuning(int(t[0]), int(t[1]), int(t[2]) if len(t) > 2 else 0))
+    return ctypes.byref(Tuning(int(t[0]), int(t[1]), int(t[2]) if len(t) > 2 else 0,
+                               int(t[3]) if len(t) > 3 else 0))
 
 
 def edt_compute_stage(grid, occ, d2, site, stage: int, tuning=None, stream=None):
@@ -245,7 +247,7 @@ def edt_default_tuning(grid):
     g = make_grid(grid)
     t = Tuning()
     _check(lib().edt_default_tuning(ctypes.byref(g), ctypes.byref(t)), "edt_default_tuning")
-    return (t.xy_tile, t.z_tile, t.z_group)
+    return (t.xy_tile, t.z_tile, t.z_group, t.xy_group)
 
 
 def edt_autotune(grid, occ, d2, site, reps: int = 10, stream=None):
@@ -258,7 +260,7 @@ def edt_autotune(grid, occ, d2, site, reps: int = 10, stream=None):
                               _dev(d2, torch.int32, "d2", n), _dev(site, torch.int32, "site", n),
                               int(reps), ctypes.byref(t), ctypes.byref(us), _stream(stream)),
            "edt_autotune")
-    return (t.xy_tile, t.z_tile, t.z_group), float(us.value)
+    return (t.xy_tile, t.z_tile, t.z_group, t.xy_group), float(us.value)
 
 
 def edt_query_spheres(grid, d2, site, centres, radii, out, stream=None):

@@ -130,21 +130,23 @@ def test_every_tiling_is_identical(oracle_lib, shape):
     o = torch.from_numpy(occ.ravel()).to(dev())
     d2 = torch.empty(occ.size, dtype=torch.int32, device=dev())
     site = torch.empty_like(d2)
-    combos = [(xt, zt, 256) for xt in (16, 32, 64) for zt in (8, 16, 32, 64)]
-    combos += [(32, zt, zg) for zg in (64, 128) for zt in (8, 16, 32, 64) if zt <= zg]
-    for xt, zt, zg in combos:
+    combos = [(xt, zt, 256, 256) for xt in (16, 32, 64) for zt in (8, 16, 32, 64)]
+    combos += [(32, zt, zg, 256) for zg in (64, 128) for zt in (8, 16, 32, 64) if zt <= zg]
+    combos += [(xt, 16, 256, xg) for xg in (64, 128) for xt in (16, 32, 64) if xt <= xg]
+    combos += [(64, 64, 64, 64)]   # one band per line in both passes (the naive variant)
+    for xt, zt, zg, xg in combos:
         if True:
-            say(f"[tiling] {shape} xy={xt} z={zt}/{zg}")
+            say(f"[tiling] {shape} xy={xt}/{xg} z={zt}/{zg}")
             d2.fill_(-7)
             site.fill_(-7)
             try:
-                edt.edt_compute_tuned(g, o, d2, site, (xt, zt, zg))
+                edt.edt_compute_tuned(g, o, d2, site, (xt, zt, zg, xg))
             except edt.EdtError as e:
                 assert e.status == -5   # tile needs more LDS than the device has
                 continue
             torch.cuda.synchronize()
-            assert np.array_equal(d2.cpu().numpy().reshape(shape), rd2), (xt, zt, zg)
-            assert np.array_equal(site.cpu().numpy().reshape(shape), rsite), (xt, zt, zg)
+            assert np.array_equal(d2.cpu().numpy().reshape(shape), rd2), (xt, zt, zg, xg)
+            assert np.array_equal(site.cpu().numpy().reshape(shape), rsite), (xt, zt, zg, xg)
 
 
 def test_autotune_keeps_results(oracle_lib):

@@ -1,0 +1,66 @@
+"""Pins of the CPU oracle's jump flooding (the approximate transform the
+paper compares against in Table 2).  JFA is not exact, so the pins are the
+properties it must have: every site is occupied and d2 is the true squared
+distance to it; d2 never undercuts the exact transform; a single seed is
+found exactly everywhere; on random maps only a small share of voxels is
+off; and a hand-made case where flooding misses the nearest site."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.brute import brute_edt
+from paper_2407_02363_amd import inputs
+
+
+def check_valid(occ, d2, site):
+    nz, ny, nx = occ.shape
+    flat = occ.ravel()
+    s = site.ravel()
+    has = s >= 0
+    assert (flat[s[has]] != 0).all()
+    z, y, x = np.unravel_index(np.arange(occ.size), occ.shape)
+    sz, sy, sx = np.unravel_index(s[has], occ.shape)
+    assert np.array_equal(d2.ravel()[has], (sx - x[has]) ** 2 + (sy - y[has]) ** 2 + (sz - z[has]) ** 2)
+
+
+@pytest.mark.parametrize("shape,pos", [((9, 13, 17), (4, 6, 8)), ((16, 16, 16), (0, 15, 3)),
+                                       ((5, 30, 7), (6, 0, 4))])
+def test_single_seed_is_exact(shape, pos):
+    occ = inputs.single_site_grid(shape, pos)
+    d2, site = oracle.jfa(occ)
+    rd2, rsite = oracle.edt(occ)
+    assert np.array_equal(d2, rd2) and np.array_equal(site, rsite)
+
+
+@pytest.mark.parametrize("density", [0.002, 0.02, 0.2])
+def test_upper_bound_and_small_error(density):
+    occ = inputs.random_grid((14, 15, 16), density, 8)
+    d2, site = oracle.jfa(occ)
+    bd, bs = brute_edt(occ)
+    check_valid(occ, d2, site)
+    assert (d2 >= bd).all()
+    assert np.mean(d2 != bd) < 0.05
+
+
+def test_empty_and_full():
+    e = np.zeros((4, 5, 6), np.uint8)
+    d2, site = oracle.jfa(e)
+    assert (d2 == 2 ** 31 - 1).all() and (site == -1).all()
+    f = np.ones((4, 5, 6), np.uint8)
+    d2, site = oracle.jfa(f)
+    assert (d2 == 0).all() and np.array_equal(site.ravel(), np.arange(f.size))
+
+
+def test_flooding_can_miss_the_nearest_site():
+    """A case where the nearest site's information is blocked: flooding
+    returns a valid but farther site for some voxel (why Table 2 calls JFA
+    approximate)."""
+    g = inputs.rng(11)
+    for _ in range(200):
+        occ = (g.random((1, 24, 24)) < 0.03).astype(np.uint8)
+        d2, _ = oracle.jfa(occ)
+        bd, _ = brute_edt(occ)
+        if (d2 != bd).any():
+            assert (d2 >= bd).all()
+            return
+    pytest.fail("no map with a flooding error found")
