@@ -334,6 +334,44 @@ def static_scene_workload(args, torch, edt, ci, cyc):
             "cycle_eager_ms": 1e3 * el / args.steps}
 
 
+def edt_comparison(args, torch, edt, inputs):
+    """The paper's EDT comparison (Table 2) on this GPU: the exact transform
+    with its tuned bands, the naive one band per line (m1 = m2 = m3 = 1), and
+    jump flooding with its error against the exact transform, on the camera
+    scene at 256 x 256 x 128 and 512 x 512 x 128 (1 cm)."""
+    res = {"paper_ms": {"256x256x128": {"pba": 3.18, "jfa": 26.67, "naive": 3.52},
+                        "512x512x128": {"pba": 7.782, "jfa": 114.47, "naive": 11.271},
+                        "hw": "GTX 1080 Ti"}}
+    dev = torch.device("cuda:0")
+    for name, grid in (("256x256x128", inputs.CYCLE_GRID),
+                       ("512x512x128", inputs.Grid(512, 512, 128, (0.0, 0.0, 0.0), 0.01))):
+        ci = inputs.cycle_inputs(0, n_frames=1, n_states=1, grid=grid)
+        g = ci.grid
+        occ = torch.zeros(g.n, dtype=torch.uint8, device=dev)
+        edt.edt_insert_points(g, occ, torch.from_numpy(ci.frames[0]).to(dev),
+                              torch.from_numpy(ci.T_map_cam).to(dev))
+        d2 = torch.empty(g.n, dtype=torch.int32, device=dev)
+        site = torch.empty_like(d2)
+        jd2 = torch.empty_like(d2)
+        jsite = torch.empty_like(d2)
+        ws = edt.new_jfa_workspace(g, dev)
+        reps = 20
+        t_exact = time_block(torch, lambda: edt.edt_compute(g, occ, d2, site), reps)
+        t_naive = time_block(torch, lambda: edt.edt_compute_tuned(g, occ, d2, site, (64, 64, 64, 64)), reps)
+        t_jfa = time_block(torch, lambda: edt.edt_jfa(g, occ, jd2, jsite, ws), reps)
+        edt.edt_compute(g, occ, d2, site)
+        torch.cuda.synchronize()
+        wrong = jd2 != d2
+        err = (jd2.double().sqrt() - d2.double().sqrt())[wrong]
+        res[name] = {"voxels": g.n, "occupied": int(occ.sum().item()),
+                     "exact_ms": t_exact, "naive_ms": t_naive, "jfa_ms": t_jfa,
+                     "jfa_wrong_fraction": float(wrong.float().mean().item()),
+                     "jfa_max_error_vox": float(err.max().item()) if err.numel() else 0.0,
+                     "jfa_mean_error_vox_where_wrong": float(err.mean().item()) if err.numel() else 0.0}
+        del occ, d2, site, jd2, jsite, ws
+    return res
+
+
 def surrogate_workload(args, torch, inputs):
     """Learned self-distance surrogate on the 128^3 self-map: exact-EDT
     labels, GPU training, worst held-out error, and look-ahead evaluation
@@ -633,6 +671,8 @@ def main():
     occupancy = occupancy_workload(args, torch, edt, ci, cyc)
     log("[bench] static scene")
     static_scene = static_scene_workload(args, torch, edt, ci, cyc)
+    log("[bench] EDT comparison (exact, naive, jump flooding)")
+    comparison = edt_comparison(args, torch, edt, inputs)
 
     batched = None
     if args.batch_maps > 0:
@@ -655,6 +695,7 @@ def main():
                       "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
            "timing": mode, "eager": eager, "latency": latency,
            "cycle_variants": variants, "occupancy": occupancy, "static_scene": static_scene,
+           "edt_comparison": comparison,
            "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
            "batched": batched, "surrogate": surrogate,
            "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",

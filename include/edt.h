@@ -102,6 +102,23 @@ int edt_insert_points(const edt_grid_t* grid, uint8_t* occ, const float* pts, in
                       const float* T_map_sensor, const uint8_t* exclude, void* stream);
 
 /*
+ * edt_jfa -- jump flooding, the approximate transform of the paper's EDT
+ * comparison (Sec. IV, Table 2), for measuring its speed and its error
+ * against edt_compute.  Seeds are the occupied voxels; for step k = S/2,
+ * S/4, ..., 1 (S the smallest power of two >= the largest axis) every voxel
+ * keeps, among the sites held by itself and the 26 voxels at offsets in
+ * {-k, 0, k}^3 inside the grid, the one closest to it (squared voxel
+ * distance, the smaller linear index on ties), all voxels reading the
+ * previous step's sites.  Output as edt_compute: site is an occupied voxel
+ * and d2 the exact squared distance to it, but the site need not be the
+ * nearest one (d2 >= the exact transform's).  ws: device,
+ * edt_jfa_workspace_bytes(grid) bytes (one int32 per voxel).
+ */
+size_t edt_jfa_workspace_bytes(const edt_grid_t* grid);
+int edt_jfa(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site, void* ws,
+            size_t ws_bytes, void* stream);
+
+/*
  * Static-scene reuse (Exp. 4: one transform serves a static scene while the
  * arm moves).  edt_compute_cached keeps, in a caller-owned cache, a snapshot
  * of which voxels were occupied when d2 / site were last computed.  Each

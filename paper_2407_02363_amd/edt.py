@@ -69,6 +69,7 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_compute_many", "edt_logodds_workspace_bytes", "edt_logodds_reset",
             "edt_update_logodds", "edt_outlier_workspace_bytes", "edt_outlier_filter",
             "edt_cache_workspace_bytes", "edt_cache_reset", "edt_compute_cached",
+            "edt_jfa_workspace_bytes", "edt_jfa",
             "edt_autotune_batched"]
 
 BATCH_MAX = 48
@@ -111,6 +112,8 @@ def lib():
                                 P], ctypes.c_int),
         "edt_outlier_workspace_bytes": ([i64], ctypes.c_size_t),
         "edt_cache_workspace_bytes": ([G], ctypes.c_size_t),
+        "edt_jfa_workspace_bytes": ([G], ctypes.c_size_t),
+        "edt_jfa": ([G, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_cache_reset": ([G, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_compute_cached": ([G, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_outlier_filter": ([P, i64, i32, ctypes.c_float, ctypes.c_float, P, P, P, P,
@@ -407,3 +410,17 @@ def edt_compute_cached(grid, occ, d2, site, cache, stream=None):
                                     _dev(d2, torch.int32, "d2", n), _dev(site, torch.int32, "site", n),
                                     _dev(cache, torch.uint8, "cache"), cache.numel(), _stream(stream)),
            "edt_compute_cached")
+
+
+def new_jfa_workspace(grid, device="cuda"):
+    n = int(lib().edt_jfa_workspace_bytes(ctypes.byref(make_grid(grid))))
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def edt_jfa(grid, occ, d2, site, ws, stream=None):
+    """Jump flooding (approximate); outputs as edt_compute."""
+    g = make_grid(grid)
+    n = _n(g)
+    _check(lib().edt_jfa(ctypes.byref(g), _dev(occ, torch.uint8, "occ", n), _dev(d2, torch.int32, "d2", n),
+                         _dev(site, torch.int32, "site", n), _dev(ws, torch.uint8, "ws"), ws.numel(),
+                         _stream(stream)), "edt_jfa")
