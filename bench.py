@@ -108,16 +108,22 @@ def time_block(torch, fn, reps):
 def time_edt_kernels(edt, torch, grid, occ, d2, site, reps):
     """Average kernel durations (ms) of the xy pass, the z pass and the whole
     transform.  The z pass rewrites its input in place, so it runs after an
-    xy pass every time: z = (xy then z) - xy, both timed back to back."""
+    xy pass every time: z = (xy then z) - xy, both timed back to back.  Each
+    figure is the median of 5 blocks of reps / 5 launches, so that one
+    disturbed block cannot skew the difference."""
     run = lambda stage: (lambda: edt.edt_compute_stage(grid, occ, d2, site, stage))
-    t_xy = time_block(torch, run(edt.STAGE_XY), reps)
 
     def pair():
         edt.edt_compute_stage(grid, occ, d2, site, edt.STAGE_XY)
         edt.edt_compute_stage(grid, occ, d2, site, edt.STAGE_Z)
 
-    t_pair = time_block(torch, pair, reps)
-    t_all = time_block(torch, run(edt.STAGE_ALL), reps)
+    per = max(4, reps // 5)
+    xs, ps, alls = [], [], []
+    for _ in range(5):
+        xs.append(time_block(torch, run(edt.STAGE_XY), per))
+        ps.append(time_block(torch, pair, per))
+        alls.append(time_block(torch, run(edt.STAGE_ALL), per))
+    t_xy, t_pair, t_all = (float(np.median(v)) for v in (xs, ps, alls))
     return t_xy, t_pair - t_xy, t_all
 
 
