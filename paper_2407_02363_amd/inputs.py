@@ -353,6 +353,16 @@ class Robot:
         f = self.fk(q)
         return f.reshape(self.n_links, 12).astype(np.float32)
 
+    def joint_frames(self, q):
+        """(axes [7, 3], origins [7, 3]) of the joints at state q, world frame:
+        joint i (1..7) sits at the origin of link i and turns about that
+        frame's z or y axis; a point on link L is moved by joints 1..L."""
+        f = self.fk(q)
+        axes = np.array([f[i + 1][:, 2] if JOINT_AXES[i] == "z" else f[i + 1][:, 1]
+                         for i in range(len(JOINT_AXES))])
+        origins = np.array([f[i + 1][:, 3] for i in range(len(JOINT_AXES))])
+        return axes, origins
+
 
 def make_robot(seed: int, base=(1.28, 1.28, 0.3), r_lo=0.04, r_hi=0.08,
                l_lo=0.20, l_hi=0.40, torso_down=False) -> Robot:
