@@ -378,6 +378,26 @@ def edt_comparison(args, torch, edt, inputs):
     return res
 
 
+def closed_loop_workload(args, inputs):
+    """Alg. 2 feeding the task-priority controller of Sec. III-F at 500 Hz: a
+    solid ball flies through the arm; every control step inserts it, runs
+    the exact EDT and the sphere queries on the GPU, and the controller's
+    joint velocity moves the arm for 2 ms."""
+    import numpy as np
+    from paper_2407_02363_amd.closed_loop import ClosedLoop, fly_through
+    ci = inputs.cycle_inputs(0, n_frames=1, n_states=4)
+    q0 = np.array([0.3, 0.6, -0.2, -0.9, 0.1, 0.5, 0.0])
+    loop = ClosedLoop(ci)
+    obstacle = fly_through(ci, q0)
+    hold, _, _ = loop.run(q0, obstacle, 750, avoid=False)
+    avoid, _, dt = loop.run(q0, obstacle, 750, avoid=True)
+    return {"workload": "256x256x128 map at 1 cm; a 6 cm solid ball at 0.5 m/s passing 5 cm from a "
+                        "sphere centre on link 4; 20 bounding spheres; activation threshold radius + "
+                        "5 cm, buffer 2 cm, gain 10/s; 750 control steps of 2 ms",
+            "min_clearance_hold_m": float(hold.min()), "min_clearance_avoid_m": float(avoid.min()),
+            "ms_per_control_step": 1e3 * dt, "max_rate_hz": 1.0 / dt}
+
+
 def surrogate_workload(args, torch, inputs):
     """Learned self-distance surrogate on the 128^3 self-map: exact-EDT
     labels, GPU training, worst held-out error, and look-ahead evaluation
@@ -679,6 +699,8 @@ def main():
     static_scene = static_scene_workload(args, torch, edt, ci, cyc)
     log("[bench] EDT comparison (exact, naive, jump flooding)")
     comparison = edt_comparison(args, torch, edt, inputs)
+    log("[bench] closed-loop avoidance")
+    closed_loop = closed_loop_workload(args, inputs)
 
     batched = None
     if args.batch_maps > 0:
@@ -701,7 +723,7 @@ def main():
                       "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
            "timing": mode, "eager": eager, "latency": latency,
            "cycle_variants": variants, "occupancy": occupancy, "static_scene": static_scene,
-           "edt_comparison": comparison,
+           "edt_comparison": comparison, "closed_loop": closed_loop,
            "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
            "batched": batched, "surrogate": surrogate,
            "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",
