@@ -391,7 +391,7 @@ def closed_loop_workload(args, inputs):
     obstacle = fly_through(ci, q0)
     hold, _, _ = loop.run(q0, obstacle, 750, avoid=False)
     avoid, _, dt = loop.run(q0, obstacle, 750, avoid=True)
-    return {"workload": "256x256x128 map at 1 cm; a 6 cm solid ball at 0.5 m/s passing 5 cm from a "
+    return {"workload": "256^3 map at 1 cm; a 6 cm solid ball at 0.5 m/s passing 5 cm from a "
                         "sphere centre on link 4; 20 bounding spheres; activation threshold radius + "
                         "5 cm, buffer 2 cm, gain 10/s; 750 control steps of 2 ms",
             "min_clearance_hold_m": float(hold.min()), "min_clearance_avoid_m": float(avoid.min()),

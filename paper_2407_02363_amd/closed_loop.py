@@ -14,6 +14,11 @@ import torch
 
 from . import controller, edt, inputs
 
+# The arm's workspace: 2.56 m on a side at 1 cm.  The arm stands at the middle
+# of the floor plane and reaches under 2 m up, so every bounding sphere stays
+# inside the map (a sphere outside it only gets a conservative zero distance).
+ARM_GRID = inputs.Grid(256, 256, 256, (0.0, 0.0, 0.0), 0.01)
+
 
 def ball_points(centre, radius, n=4000, seed=0, step=0.005):
     """Points of a solid ball (map frame): n points on its surface plus a
@@ -29,10 +34,10 @@ def ball_points(centre, radius, n=4000, seed=0, step=0.005):
 
 
 class ClosedLoop:
-    def __init__(self, ci, device="cuda:0", margin=0.05, buffer=0.02, target_offset=0.05, gain=10.0,
+    def __init__(self, ci, grid=ARM_GRID, device="cuda:0", margin=0.05, buffer=0.02, target_offset=0.05, gain=10.0,
                  hold_gain=2.0, qdot_max=2.0, dt=0.002):
         self.ci = ci
-        self.g = ci.grid
+        self.g = grid
         self.dev = torch.device(device)
         d = self.dev
         n = self.g.n

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2407_02363_amd import inputs
-from paper_2407_02363_amd.closed_loop import ClosedLoop, fly_through
+from paper_2407_02363_amd.closed_loop import ARM_GRID, ClosedLoop, fly_through
 from tests.gpu_util import say
 
 pytestmark = pytest.mark.gpu
@@ -15,6 +15,9 @@ pytestmark = pytest.mark.gpu
 def test_avoidance_keeps_the_arm_clear():
     ci = inputs.cycle_inputs(0, n_frames=1, n_states=4)
     q0 = np.array([0.3, 0.6, -0.2, -0.9, 0.1, 0.5, 0.0])
+    C = inputs.sphere_centres(ci.robot, q0, ci.sphere_links, ci.sphere_local)
+    top = np.array([ARM_GRID.nx, ARM_GRID.ny, ARM_GRID.nz]) * ARM_GRID.voxel
+    assert (C > 0.2).all() and (C < top - 0.2).all()    # the whole arm, and the ball, in the map
     loop = ClosedLoop(ci)
     obstacle = fly_through(ci, q0)
     steps = 750
