@@ -35,7 +35,9 @@ __global__ __launch_bounds__(NTZ) void k_edt_z(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
     if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
-    const int T = xcd_remap(blockIdx.x, s.total);
+    // z tiles share no cache lines, so they go to the XCDs in launch order:
+    // neighbouring rows (and their uneven work) spread over all eight
+    const int T = (int)blockIdx.x;
     const EdtMap& d = s.m[map_of(s, T)];
     edt_z_tile<TW, WIDE, NTZ>(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, lds);
 }

@@ -18,16 +18,17 @@
 //
 // Banding (the m2 / m3 bands of the paper's steps 2 and 3).  Each column is
 // cut into NB bands; one thread per (column, band) builds the band's own
-// envelope with a stack.  The band envelopes of a column are then merged in
-// log2(NB) rounds of independent pairwise merges: the envelope of two
-// neighbouring groups keeps a prefix of the left one and a suffix of the
-// right one, found by popping dominated sites on either side of the seam
-// until neither side pops.  Each (column, band) thread then locates the
-// envelope site of its first position (walking from its own band's range,
-// then a binary search) and marches through its positions with a
-// strength-reduced test.  The stacks keep packed self-contained entries
-// (position | x' << 10 [| y' << 20]), so a key is recomputed from an entry
-// and no side table is needed.
+// envelope with a stack.  The band envelopes of a column are then merged:
+// the envelope of two neighbouring chains keeps a prefix of the left one and
+// a suffix of the right one, found by popping dominated sites on either side
+// of the seam until neither side pops.  One thread per group of up to 4
+// bands stitches the group's bands in order (a short chain of dependent
+// steps); the groups then merge in log2(NB / 4) rounds of independent pairs.
+// Each (column, band) thread then locates the envelope site of its first
+// position (walking from its own band's range, then a binary search) and
+// marches through its positions with a strength-reduced test.  The stacks
+// keep packed self-contained entries (position | x' << 10 [| y' << 20]), so a
+// key is recomputed from an entry and no side table is needed.
 //
 //   xy tile   work-group = (z slice, TW consecutive columns).  The slice
 //             arrives as 16-byte loads turned into a bit string in LDS; one
@@ -254,19 +255,136 @@ __device__ void link_bands(int col, const BandMeta& m)
     }
 }
 
-// All bands of every column of the tile: log2(NB) rounds of pairwise group
-// merges (groups of one round are independent), then the band links.
+// The envelope of bands [b0, b0 + G) of one column by one thread, left to
+// right: the merged chain of bands [b0, r) takes band r by popping dominated
+// sites on either side of the seam (the rule of merge_group; the envelope is
+// unique, so the order of merging does not change it).  The chain's last two
+// sites stay in registers; the range of every band finished with is written
+// back.  After the build every band's range is [0, top).
+template <int TW, int G, bool WIDE, class KeyF>
+__device__ void stitch_bands(const uint32_t* ent, int L, int col, const BandMeta& m, const KeyF& key,
+                             int b0)
+{
+    auto E = [&](int b, int i) { return ent[(b * L + i) * TW + col]; };
+    auto LO = [&](int b) -> int16_t& { return m.lo[b * TW + col]; };
+    auto HI = [&](int b) -> int16_t& { return m.hi[b * TW + col]; };
+    // last non-empty band before b (exists whenever the chain holds a site there)
+    auto prev_band = [&](int b) {
+        --b;
+        while (b > b0 && LO(b) == HI(b)) --b;
+        return b;
+    };
+    int top[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) top[i] = HI(b0 + i);
+    int t = 0, lo_t = 0, hi_t = 0, cnt = 0;   // the chain's tail band, its range, chain length
+    int p0 = 0, k0 = 0, p1 = 0, k1 = 0;       // the chain's second-to-last and last sites
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const int r = b0 + i;
+        const int n = top[i];
+        if (n == 0) continue;
+        const uint32_t ec = E(r, 0), ed = E(r, n > 1 ? 1 : 0);
+        const uint32_t ey = E(r, n > 1 ? n - 2 : 0), ez = E(r, n - 1);
+        if (cnt == 0) {
+            t = r;
+            lo_t = 0;
+            hi_t = n;
+            cnt = n;
+            p1 = (int)(ez & POS_MASK);
+            k1 = key(ez);
+            p0 = (int)(ey & POS_MASK);
+            k0 = key(ey);
+            continue;
+        }
+        int lo_r = 0, rem = n;
+        int pc = (int)(ec & POS_MASK), kc = key(ec);
+        int pd = (int)(ed & POS_MASK), kd = key(ed);
+        for (;;) {
+            if (cnt >= 2 && dominated<WIDE>(p0, k0, p1, k1, pc, kc)) {
+                --hi_t;
+                --cnt;
+                p1 = p0;
+                k1 = k0;
+                if (hi_t == lo_t) {
+                    HI(t) = (int16_t)hi_t;
+                    t = prev_band(t);
+                    lo_t = LO(t);
+                    hi_t = HI(t);
+                }
+                if (cnt >= 2) {
+                    uint32_t e;
+                    if (hi_t - lo_t >= 2) {
+                        e = E(t, hi_t - 2);
+                    } else {
+                        const int b = prev_band(t);
+                        e = E(b, HI(b) - 1);
+                    }
+                    p0 = (int)(e & POS_MASK);
+                    k0 = key(e);
+                }
+                continue;
+            }
+            if (rem >= 2 && dominated<WIDE>(p1, k1, pc, kc, pd, kd)) {
+                ++lo_r;
+                --rem;
+                pc = pd;
+                kc = kd;
+                if (rem >= 2) {
+                    const uint32_t e = E(r, lo_r + 1);
+                    pd = (int)(e & POS_MASK);
+                    kd = key(e);
+                }
+                continue;
+            }
+            break;
+        }
+        HI(t) = (int16_t)hi_t;
+        LO(r) = (int16_t)lo_r;
+        // band r becomes the chain's tail; its last two sites are untouched
+        // unless a single one is left
+        cnt += rem;
+        if (rem >= 2) {
+            p1 = (int)(ez & POS_MASK);
+            k1 = key(ez);
+            p0 = (int)(ey & POS_MASK);
+            k0 = key(ey);
+        } else {
+            p0 = p1;
+            k0 = k1;
+            p1 = pc;
+            k1 = kc;
+        }
+        t = r;
+        lo_t = lo_r;
+        hi_t = n;
+    }
+}
+
+// All bands of every column of the tile, then the band links.  Groups of up
+// to 4 bands are stitched in sequence, one thread per group; the groups then
+// merge in log2(NB / 4) rounds of independent pairs, so the chain of
+// dependent steps stays short for any band count.
 template <int TW, int NB, bool WIDE, class KeyF>
 __device__ __forceinline__ void merge_all(const uint32_t* ent, int L, int col, int band, bool live,
                                           const BandMeta& m, const KeyF& key)
 {
-    for (int half = 1; half < NB; half <<= 1) {
-        const int span = half << 1;
-        if (live && (band & (span - 1)) == 0)
-            merge_group<TW, WIDE>(ent, L, col, m, key, band, band + half, band + span);
+    if constexpr (NB <= 4) {
+        if (live && band == col * NB / TW) {
+            stitch_bands<TW, NB, WIDE>(ent, L, col, m, key, 0);
+            link_bands<TW, NB>(col, m);
+        }
+    } else {
+        if (live && (band & 3) == 0) stitch_bands<TW, 4, WIDE>(ent, L, col, m, key, band);
         __syncthreads();
+        for (int half = 4; half < NB; half <<= 1) {
+            const int span = half << 1;
+            if (live && (band & (span - 1)) == 0)
+                merge_group<TW, WIDE>(ent, L, col, m, key, band, band + half, band + span);
+            __syncthreads();
+        }
+        if (live && band == col * NB / TW) link_bands<TW, NB>(col, m);
     }
-    if (live && band == col * NB / TW) link_bands<TW, NB>(col, m);
     __syncthreads();
 }
 
@@ -640,7 +758,9 @@ __device__ __forceinline__ void edt_z_tile(int32_t* d2, int32_t* site, int nx, i
             // along a run of one site, (q - p)^2 + h grows by 2(q - p) + 1
             dd = k - 2 * mul24(q, p) + mul24(q, q);
             inc = 2 * (q - p) + 1;
-            ss = (int32_t)(((e >> 10) & POS_MASK) + (uint32_t)nx * ((e >> 20) + (uint32_t)ny * (uint32_t)p));
+            // x' + nx (y' + ny z'): 24-bit operands, product below 2^31
+            ss = (int32_t)(((e >> 10) & POS_MASK) +
+                           __umul24((unsigned)nx, (e >> 20) + __umul24((unsigned)ny, (unsigned)p)));
         },
         [&](int) {
             *od = dd;
