@@ -98,6 +98,17 @@ struct KeyZ {
     }
 };
 
+// Band of this thread.  With tiles of 64 columns or more a wave is one band,
+// and saying so lets the compiler keep band-wide positions and addresses in
+// scalar registers.
+template <int TW>
+__device__ __forceinline__ int band_of()
+{
+    const int b = (int)threadIdx.x / TW;
+    if constexpr (TW % 64 == 0) return __builtin_amdgcn_readfirstlane(b);
+    return b;
+}
+
 // Band-local envelope of sites pushed in increasing position; the two
 // topmost entries stay in registers.
 template <int TW, bool WIDE, class KeyF>
@@ -636,7 +647,7 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
 
     // ---- step 2, band-local: x' per row from the row records, then push
     const int col = threadIdx.x % TW;
-    const int band = threadIdx.x / TW;
+    const int band = band_of<TW>();
     const int xc = x0 + col;
     const bool live = xc < nx;
     const KeyY key{xc};
@@ -702,7 +713,7 @@ __device__ __forceinline__ void edt_z_tile(int32_t* d2, int32_t* site, int nx, i
     const int y = T / ntx;
     const int x0 = (T - y * ntx) * TW;
     const int col = threadIdx.x % TW;
-    const int band = threadIdx.x / TW;
+    const int band = band_of<TW>();
     const int xc = x0 + col;
     const bool live = xc < nx;
     const KeyZ key{xc, y};
@@ -718,10 +729,13 @@ __device__ __forceinline__ void edt_z_tile(int32_t* d2, int32_t* site, int nx, i
             // chunks of CH positions, software-pipelined: the next chunk's
             // loads (clamped into the band) are in flight while this chunk is
             // pushed, with the chunk loop fully unrolled
+            // row pointers are band-wide (scalar when a wave is one band),
+            // the lane adds its column
+            const uint32_t* tile_in = reinterpret_cast<const uint32_t*>(site) + ((size_t)y * nx + x0);
             auto load = [&](uint32_t (&v)[CH], int zb) {
 #pragma unroll
                 for (int i = 0; i < CH; ++i)   // z * plane < 2^32 with z < 2^10, plane <= 2^20
-                    v[i] = (uint32_t)site[base + __umul24((unsigned)min(zb + i, q1 - 1), plane32)];
+                    v[i] = (tile_in + __umul24((unsigned)min(zb + i, q1 - 1), plane32))[col];
             };
             uint32_t cur[CH], nxt[CH];
             load(cur, q0);
@@ -750,8 +764,9 @@ __device__ __forceinline__ void edt_z_tile(int32_t* d2, int32_t* site, int nx, i
     if (!live || q0 >= q1) return;
     int dd = 0, inc = 0;
     int32_t ss = 0;
-    int32_t* od = d2 + base + (size_t)q0 * plane;
-    int32_t* os = site + base + (size_t)q0 * plane;
+    // band-wide row pointers (scalar when a wave is one band)
+    int32_t* row_d2 = d2 + ((size_t)y * nx + x0) + (size_t)q0 * plane;
+    int32_t* row_site = site + ((size_t)y * nx + x0) + (size_t)q0 * plane;
     query_band<TW, NB>(
         ent, L, col, meta, q0, q1, key,
         [&](int q, uint32_t e, int p, int k) {
@@ -763,10 +778,10 @@ __device__ __forceinline__ void edt_z_tile(int32_t* d2, int32_t* site, int nx, i
                            __umul24((unsigned)nx, (e >> 20) + __umul24((unsigned)ny, (unsigned)p)));
         },
         [&](int) {
-            *od = dd;
-            *os = ss;
-            od += plane;
-            os += plane;
+            row_d2[col] = dd;
+            row_site[col] = ss;
+            row_d2 += plane;
+            row_site += plane;
             dd += inc;
             inc += 2;
         },
