@@ -257,8 +257,8 @@ int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t
                 void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Tile widths of the two EDT kernels: columns per 256-thread work-group.
- * Each column of a tile is split into 256 / tile bands, the m2 / m3 bands
+ * Tile widths of the two EDT kernels: columns per work-group.  Each column
+ * of a tile is split into group / tile bands, the m2 / m3 bands
  * of the paper's steps 2 and 3 (Sec. III-C): every band builds its own
  * envelope of proximate sites, neighbouring envelopes are merged, and every
  * band queries its own positions.  xy_tile is one of 16, 32, 64; z_tile one
@@ -272,7 +272,8 @@ typedef struct edt_tuning_t {
     int32_t z_tile;
     int32_t z_group;   /* threads per z work-group: 64, 128 or 256 (0 = 256);
                           z_tile <= z_group, bands per column = z_group / z_tile */
-    int32_t xy_group;  /* threads per xy work-group: 64, 128 or 256 (0 = 256);
+    int32_t xy_group;  /* threads per xy work-group: 64, 128, 256 (0 = 256) or 512
+                          with xy_tile >= 32;
                           xy_tile <= xy_group, bands per column = xy_group / xy_tile.
                           xy_tile = xy_group and z_tile = z_group give one band per
                           line in both passes, the paper's naive m1 = m2 = m3 = 1 */

@@ -130,7 +130,7 @@ bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt)
     constexpr size_t LDS_MAX = 160 * 1024 - 8192;
     if (pass == 1) {
         if (tw != 16 && tw != 32 && tw != 64) return false;
-        if (nt != 64 && nt != 128 && nt != 256) return false;
+        if (nt != 64 && nt != 128 && nt != 256 && !(nt == 512 && tw >= 32)) return false;
         if (tw > nt) return false;
         return xy_lds(tw, g->ny, nt) <= LDS_MAX;
     }
@@ -142,14 +142,19 @@ bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt)
 
 EdtTuning default_tuning(const edt_grid_t* g)
 {
-    // measured on MI355X: 32-wide xy tiles up to 256 rows, 16-wide beyond;
-    // z tiles keep about 32 positions per band
+    // measured on MI355X: 32-wide xy tiles up to 256 rows; up to 512 rows the
+    // same tiles with 512 threads (32 rows per band, and each slice staged by
+    // half as many work-groups as with 16-wide tiles); 16-wide beyond.  z
+    // tiles keep about 32 positions per band
     EdtTuning t;
-    t.xy_tw = g->ny <= 256 ? 32 : 16;
+    t.xy_tw = g->ny <= 512 ? 32 : 16;
+    t.xy_nt = g->ny > 256 && g->ny <= 512 ? 512 : 256;
     t.z_tw = g->nz <= 128 ? 64 : (g->nz <= 256 ? 32 : 16);
     t.z_nt = 256;
-    t.xy_nt = 256;
-    if (!tile_ok(1, t.xy_tw, g, 256)) t.xy_tw = 16;
+    if (!tile_ok(1, t.xy_tw, g, t.xy_nt)) {
+        t.xy_tw = 16;
+        t.xy_nt = 256;
+    }
     if (!tile_ok(2, t.z_tw, g, t.z_nt)) t.z_tw = 8;
     return t;
 }
@@ -187,7 +192,12 @@ int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMap
 
 int launch_edt_xy_set(const EdtMapSet& s, int tw, int nt, hipStream_t st)
 {
-    if (nt == 256) {
+    if (nt == 512) {
+        switch (tw) {
+            case 64: return launch_xy_tw<64, 512>(s, st);
+            case 32: return launch_xy_tw<32, 512>(s, st);
+        }
+    } else if (nt == 256) {
         switch (tw) {
             case 64: return launch_xy_tw<64, 256>(s, st);
             case 32: return launch_xy_tw<32, 256>(s, st);

@@ -681,17 +681,18 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
 
     // ---- step 3: every row of the band
     if (!live || q0 >= q1) return;
-    uint32_t* out = xy + (size_t)z * ny * nx + (size_t)q0 * nx + xc;
+    // band-wide row pointer (scalar when a wave is one band); the lane adds its column
+    uint32_t* row = xy + ((size_t)z * ny + q0) * nx + x0;
     uint32_t val = 0;
     query_band<TW, NB>(
         ent, L, col, meta, q0, q1, key,
         [&](int, uint32_t e, int, int) { val = (e >> 10) | ((e & POS_MASK) << 16); },
         [&](int) {
-            *out = val;
-            out += nx;
+            row[col] = val;
+            row += nx;
         },
         [&](int a, int b) {
-            for (int q = a; q < b; ++q, out += nx) *out = XY_NONE;
+            for (int q = a; q < b; ++q, row += nx) row[col] = XY_NONE;
         });
 }
 

@@ -17,6 +17,7 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, EdtTuning> g_tuned;
 
 const int XY_TILES[] = {16, 32, 64};
+const int XY_GROUPS[] = {256, 512};
 const int Z_TILES[] = {8, 16, 32, 64};
 const int Z_GROUPS[] = {64, 128, 256};
 
@@ -99,13 +100,15 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
     }
     const hipStream_t st = as_stream(stream);
     float best_xy = 1e30f, best_z = 1e30f;
-    int bxy = 0, bz = 0, bnt = 0;
-    for (int tw : XY_TILES) {
-        if (!tile_ok(1, tw, grid, 256)) continue;
-        float ms = 0.0f;
-        rc = time_pass(grid, occ, d2, site, 1, tw, 256, reps, st, &ms);
-        if (rc) return rc;
-        if (ms < best_xy) { best_xy = ms; bxy = tw; }
+    int bxy = 0, bxnt = 0, bz = 0, bnt = 0;
+    for (int nt : XY_GROUPS) {
+        for (int tw : XY_TILES) {
+            if (!tile_ok(1, tw, grid, nt)) continue;
+            float ms = 0.0f;
+            rc = time_pass(grid, occ, d2, site, 1, tw, nt, reps, st, &ms);
+            if (rc) return rc;
+            if (ms < best_xy) { best_xy = ms; bxy = tw; bxnt = nt; }
+        }
     }
     for (int nt : Z_GROUPS) {
         for (int tw : Z_TILES) {
@@ -122,10 +125,10 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz, bnt, 256};
+        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz, bnt, bxnt};
     }
     // leave a complete transform in d2 / site
-    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), bxy, 256, st);
+    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), bxy, bxnt, st);
     if (!rc) rc = launch_edt_z(grid, d2, site, bz, bnt, st);
     if (rc) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) {
@@ -136,7 +139,7 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
         best->xy_tile = bxy;
         best->z_tile = bz;
         best->z_group = bnt;
-        best->xy_group = 256;
+        best->xy_group = bxnt;
     }
     if (best_us) *best_us = 1000.0f * (best_xy + best_z);
     return EDT_OK;
