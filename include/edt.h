@@ -270,7 +270,8 @@ int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t
 typedef struct edt_tuning_t {
     int32_t xy_tile;
     int32_t z_tile;
-    int32_t z_group;   /* threads per z work-group: 64, 128 or 256 (0 = 256);
+    int32_t z_group;   /* threads per z work-group: 64, 128, 256 (0 = 256) or 512
+                          with z_tile = 64;
                           z_tile <= z_group, bands per column = z_group / z_tile */
     int32_t xy_group;  /* threads per xy work-group: 64, 128, 256 (0 = 256) or 512
                           with xy_tile >= 32;

@@ -135,7 +135,7 @@ bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt)
         return xy_lds(tw, g->ny, nt) <= LDS_MAX;
     }
     if (tw != 8 && tw != 16 && tw != 32 && tw != 64) return false;
-    if (nt != 64 && nt != 128 && nt != 256) return false;
+    if (nt != 64 && nt != 128 && nt != 256 && !(nt == 512 && tw == 64)) return false;
     if (tw > nt) return false;
     return z_lds(tw, g->nz, nt) <= LDS_MAX;
 }
@@ -222,6 +222,7 @@ int launch_edt_xy_set(const EdtMapSet& s, int tw, int nt, hipStream_t st)
 
 int launch_edt_z_set(const EdtMapSet& s, int tw, int nt, hipStream_t st)
 {
+    if (nt == 512 && tw == 64) return launch_z_tw<64, 512>(s, st);
     if (nt == 256) {
         switch (tw) {
             case 64: return launch_z_tw<64, 256>(s, st);

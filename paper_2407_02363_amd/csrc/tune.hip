@@ -19,7 +19,7 @@ std::map<std::tuple<int, int, int>, EdtTuning> g_tuned;
 const int XY_TILES[] = {16, 32, 64};
 const int XY_GROUPS[] = {256, 512};
 const int Z_TILES[] = {8, 16, 32, 64};
-const int Z_GROUPS[] = {64, 128, 256};
+const int Z_GROUPS[] = {64, 128, 256, 512};
 
 // Average time (ms) of `reps` launches of one pass with tile tw.
 int time_pass(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, int32_t* site, int pass,

@@ -135,6 +135,7 @@ def test_every_tiling_is_identical(oracle_lib, shape):
     combos += [(xt, 16, 256, xg) for xg in (64, 128) for xt in (16, 32, 64) if xt <= xg]
     combos += [(64, 64, 64, 64)]   # one band per line in both passes (the naive variant)
     combos += [(xt, 64, 256, 512) for xt in (32, 64)]   # 512-thread xy work-groups
+    combos += [(32, 64, 512, 256)]                       # 512-thread z work-groups
     for xt, zt, zg, xg in combos:
         if True:
             say(f"[tiling] {shape} xy={xt}/{xg} z={zt}/{zg}")
