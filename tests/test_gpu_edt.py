@@ -151,6 +151,43 @@ def test_every_tiling_is_identical(oracle_lib, shape):
             assert np.array_equal(site.cpu().numpy().reshape(shape), rsite), (xt, zt, zg, xg)
 
 
+@pytest.mark.parametrize("seed,gap", [(0, False), (1, False), (2, True)])
+def test_sparse_slices_every_band_layout(oracle_lib, seed, gap):
+    """Most slices empty, the rest holding one to three voxels far apart:
+    along z every column sees few sites with very uneven heights, so bands
+    are often empty or hold a single site and merges pop across several
+    bands (with gap, only the first and last 24 slices hold voxels, so the
+    middle bands are empty).  Every z tiling (1 to 8 bands per column) and
+    both xy group sizes must match the oracle."""
+    import torch
+    from paper_2407_02363_amd import edt
+    from tests.gpu_util import dev, grid_of
+    shape = (128, 40, 96)
+    g = inputs.rng(100 + seed)
+    occ = np.zeros(shape, np.uint8)
+    for z in range(shape[0]):
+        if gap and 24 <= z < shape[0] - 24:
+            continue
+        if g.uniform() < (0.3 if gap else 0.12):
+            for _ in range(int(g.integers(1, 4))):
+                occ[z, g.integers(0, shape[1]), g.integers(0, shape[2])] = 1
+    rd2, rsite = oracle_lib.edt(occ)
+    grid = grid_of(shape)
+    o = torch.from_numpy(occ.ravel()).to(dev())
+    d2 = torch.empty(occ.size, dtype=torch.int32, device=dev())
+    site = torch.empty_like(d2)
+    combos = [(32, zt, zg, 256) for zg in (64, 128, 256) for zt in (8, 16, 32, 64) if zt <= zg]
+    combos += [(32, 64, 512, 256), (32, 64, 256, 512), (64, 64, 256, 512)]
+    for xt, zt, zg, xg in combos:
+        say(f"[sparse slices] seed {seed} gap {gap} xy={xt}/{xg} z={zt}/{zg}")
+        d2.fill_(-7)
+        site.fill_(-7)
+        edt.edt_compute_tuned(grid, o, d2, site, (xt, zt, zg, xg))
+        torch.cuda.synchronize()
+        assert np.array_equal(d2.cpu().numpy().reshape(shape), rd2), (xt, zt, zg, xg)
+        assert np.array_equal(site.cpu().numpy().reshape(shape), rsite), (xt, zt, zg, xg)
+
+
 def test_autotune_keeps_results(oracle_lib):
     import torch
     from paper_2407_02363_amd import edt
