@@ -105,6 +105,13 @@ def time_block(torch, fn, reps):
     return a.elapsed_time(b) / reps
 
 
+def time_median(torch, fn, reps, blocks=5):
+    """Median over `blocks` blocks of time_block(fn, reps // blocks), so that
+    one disturbed block cannot skew the figure."""
+    per = max(2, reps // blocks)
+    return float(np.median([time_block(torch, fn, per) for _ in range(blocks)]))
+
+
 def time_edt_kernels(edt, torch, grid, occ, d2, site, reps):
     """Average kernel durations (ms) of the xy pass, the z pass and the whole
     transform.  The z pass rewrites its input in place, so it runs after an
@@ -361,10 +368,10 @@ def edt_comparison(args, torch, edt, inputs):
         jd2 = torch.empty_like(d2)
         jsite = torch.empty_like(d2)
         ws = edt.new_jfa_workspace(g, dev)
-        reps = 20
-        t_exact = time_block(torch, lambda: edt.edt_compute(g, occ, d2, site), reps)
-        t_naive = time_block(torch, lambda: edt.edt_compute_tuned(g, occ, d2, site, (64, 64, 64, 64)), reps)
-        t_jfa = time_block(torch, lambda: edt.edt_jfa(g, occ, jd2, jsite, ws), reps)
+        reps = 25
+        t_exact = time_median(torch, lambda: edt.edt_compute(g, occ, d2, site), reps)
+        t_naive = time_median(torch, lambda: edt.edt_compute_tuned(g, occ, d2, site, (64, 64, 64, 64)), reps)
+        t_jfa = time_median(torch, lambda: edt.edt_jfa(g, occ, jd2, jsite, ws), reps)
         edt.edt_compute(g, occ, d2, site)
         torch.cuda.synchronize()
         wrong = jd2 != d2

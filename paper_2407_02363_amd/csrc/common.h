@@ -89,13 +89,17 @@ int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMap
 int launch_edt_xy_set(const EdtMapSet& s, int tw, int nt, hipStream_t st);
 int launch_edt_z_set(const EdtMapSet& s, int tw, int nt, hipStream_t st);
 
-// Work-group index remap so that consecutive logical tiles land on the same
-// XCD (the dispatcher deals work-groups to the 8 XCDs round-robin).  A
-// bijection of [0, G).
-__device__ inline int xcd_remap(int b, int G)
+// Work-group index remap: chunks of C consecutive logical tiles each land on
+// one XCD (the dispatcher deals work-groups to the 8 XCDs round-robin), and
+// consecutive chunks go to consecutive XCDs, so neighbouring tiles share an
+// L2 while uneven work spreads over all eight.  A bijection of [0, G): the
+// tail that does not fill 8 whole chunks keeps launch order.
+__device__ inline int xcd_chunk_remap(int b, int G, int C)
 {
-    const int per = G >> 3, rem = G & 7, xcd = b & 7, k = b >> 3;
-    return xcd * per + (xcd < rem ? xcd : rem) + k;
+    const int full = G / (8 * C) * (8 * C);
+    if (b >= full) return b;
+    const int xcd = b & 7, k = b >> 3;
+    return (k / C) * 8 * C + xcd * C + k % C;
 }
 
 }  // namespace edtmi

@@ -24,7 +24,10 @@ __global__ __launch_bounds__(NTX) void k_edt_xy(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
     if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
-    const int T = xcd_remap(blockIdx.x, s.total);
+    // the tiles of a slice read the same occupancy bytes: chunks of 16 tiles
+    // (one or two slices) share an XCD's L2, and the slices, whose work is
+    // very uneven, rotate over the XCDs
+    const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
     const EdtMap& d = s.m[map_of(s, T)];
     edt_xy_tile<TW, WIDE, NTX>(d.occ, reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny, d.nz, d.ntx,
                                T - d.begin, lds);
