@@ -38,9 +38,10 @@ __global__ __launch_bounds__(NTZ) void k_edt_z(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
     if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
-    // z tiles share no cache lines, so they go to the XCDs in launch order:
-    // neighbouring rows (and their uneven work) spread over all eight
-    const int T = (int)blockIdx.x;
+    // tiles narrower than 64 columns share cache lines with their neighbours:
+    // the tiles of 64 columns of a row stay on one XCD, and rows (whose work
+    // is very uneven) rotate over all eight
+    const int T = TW >= 64 ? (int)blockIdx.x : xcd_chunk_remap(blockIdx.x, s.total, 64 / TW);
     const EdtMap& d = s.m[map_of(s, T)];
     edt_z_tile<TW, WIDE, NTZ>(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, lds);
 }
