@@ -543,7 +543,7 @@ def main():
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--batch-maps", type=int, default=32, help="0 = skip the batched workload")
     ap.add_argument("--batch-cycles", type=int, default=1000)
-    ap.add_argument("--surrogate-train", type=int, default=262144,
+    ap.add_argument("--surrogate-train", type=int, default=1048576,
                     help="training states of the surrogate (0 = skip the surrogate workload)")
     ap.add_argument("--surrogate-epochs", type=int, default=60)
     ap.add_argument("--lookahead-cycles", type=int, default=1000)
