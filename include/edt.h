@@ -249,8 +249,9 @@ size_t edt_workspace_bytes(const edt_grid_t* grid);
  *   site  int32 [nx*ny*nz] out: linear index of the nearest site; among
  *         equidistant sites the smallest linear index.
  *   If the map has no occupied voxel: d2 = INT32_MAX and site = -1
- *   everywhere.  Both outputs are fully overwritten; they must not overlap
- *   occ or each other.  ws / ws_bytes: workspace of at least
+ *   everywhere.  Both outputs are fully overwritten (d2 also serves as
+ *   scratch in between); they must not overlap occ or each other.  ws /
+ *   ws_bytes: workspace of at least
  *   edt_workspace_bytes(grid) bytes (may be NULL when that is 0).
  */
 int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t* site,
@@ -293,7 +294,9 @@ int edt_compute_tuned(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, i
  * callers that pipeline the passes of several maps.
  *   stage EDT_STAGE_XY: steps 1-3 of Sec. III-C in every z slice; writes the
  *         2D nearest site of each voxel, packed x' | y' << 16 (0xFFFFFFFF if
- *         the slice is empty), into site; d2 is not touched.
+ *         the slice is empty), into site.  With nx >= 64 it first writes
+ *         per-row records of step 1 (12 bytes per 64 columns) into d2, as
+ *         scratch; d2 holds nothing meaningful after this stage.
  *   stage EDT_STAGE_Z: step 4 (steps 2-3 along z); reads that packed form
  *         from site and overwrites d2 and site with the final result.
  *   stage EDT_STAGE_ALL: both, identical to edt_compute_tuned.

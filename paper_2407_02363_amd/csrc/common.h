@@ -59,7 +59,8 @@ EdtTuning default_tuning(const edt_grid_t* g);   // heuristic
 EdtTuning current_tuning(const edt_grid_t* g);   // autotuned if cached, else heuristic
 bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt);   // pass 1 = xy, 2 = z
 bool needs_wide(const edt_grid_t* g);
-int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, int nt,
+// The xy pass of one map into xy (the site buffer); d2 may serve as scratch.
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, uint32_t* xy, int tw, int nt,
                   hipStream_t st, const int* gate = nullptr);
 int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt, hipStream_t st,
                  const int* gate = nullptr);

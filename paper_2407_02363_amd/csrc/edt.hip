@@ -566,7 +566,7 @@ int edt_compute_stage(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, i
     }
     const hipStream_t st = as_stream(stream);
     if (stage & EDT_STAGE_XY) {
-        rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, t.xy_nt, st);
+        rc = launch_edt_xy(grid, occ, d2, reinterpret_cast<uint32_t*>(site), t.xy_tw, t.xy_nt, st);
         if (rc) return rc;
     }
     if (stage & EDT_STAGE_Z) rc = launch_edt_z(grid, d2, site, t.z_tw, t.z_nt, st);
@@ -665,7 +665,7 @@ int edt_compute_cached(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, 
     else
         hipLaunchKernelGGL(k_cache_compare<false>, dim3(blocks), dim3(256), 0, st, occ, snap, n, flags);
     if ((rc = check_launch("k_cache_compare"))) return rc;
-    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), t.xy_tw, t.xy_nt, st, flags);
+    rc = launch_edt_xy(grid, occ, d2, reinterpret_cast<uint32_t*>(site), t.xy_tw, t.xy_nt, st, flags);
     if (!rc) rc = launch_edt_z(grid, d2, site, t.z_tw, t.z_nt, st, flags);
     if (rc) return rc;
     hipLaunchKernelGGL(k_cache_end, dim3(1), dim3(1), 0, st, flags);

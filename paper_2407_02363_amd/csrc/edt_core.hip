@@ -33,6 +33,37 @@ __global__ __launch_bounds__(NTX) void k_edt_xy(EdtMapSet s)
                                T - d.begin, lds);
 }
 
+// Row records (step 1) of every map of the set: each wave takes
+// record_rows_per_wave(nx) whole rows of one map, four waves per work-group;
+// s.m[i].begin is the map's first wave.
+__global__ __launch_bounds__(256) void k_row_records(EdtMapSet s)
+{
+    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
+    const int wv = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+    if (wv >= s.total) return;
+    const EdtMap& d = s.m[map_of(s, wv)];
+    const int per = record_rows_per_wave(d.occ, d.nx);
+    const int row0 = (wv - d.begin) * per;
+    const int nrows = min(per, d.ny * d.nz - row0);
+    if (record_words(d.occ, d.nx))
+        row_summary_words(d.occ, d.nx, (size_t)row0, nrows, row_records(d.d2, d.nx, d.ny, d.nz));
+    else
+        row_summary(d.occ, d.nx, (size_t)row0, nrows, row_records(d.d2, d.nx, d.ny, d.nz));
+}
+
+// Steps 2-3 from the row records.
+template <int TW, bool WIDE, int NTX>
+__global__ __launch_bounds__(NTX) void k_edt_xy_rows(EdtMapSet s)
+{
+    extern __shared__ uint32_t lds[];
+    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
+    // as in k_edt_xy: chunks of 16 tiles per XCD, rotating over the XCDs
+    const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
+    const EdtMap& d = s.m[map_of(s, T)];
+    edt_xy_tile_rows<TW, WIDE, NTX>(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site),
+                                    d.nx, d.ny, d.ntx, T - d.begin, lds);
+}
+
 template <int TW, bool WIDE, int NTZ>
 __global__ __launch_bounds__(NTZ) void k_edt_z(EdtMapSet s)
 {
@@ -62,9 +93,38 @@ int allow_lds(K kernel, bool& done)
     return EDT_OK;
 }
 
+// Step 1 once per row when every map's rows are at least 64 voxels long (so
+// the records fit in its d2 buffer), else inside every tile from the slice.
+bool rows_first(const EdtMapSet& s)
+{
+    for (int i = 0; i < s.n; ++i)
+        if (s.m[i].nx < 64 || !s.m[i].d2) return false;
+    return true;
+}
+
 template <int TW, bool WIDE, int NTX>
 int launch_xy_w(const EdtMapSet& s, hipStream_t st)
 {
+    if (rows_first(s)) {
+        static thread_local EdtMapSet r;   // the maps counted in waves (2.3 KiB: off the stack)
+        r = s;
+        int waves = 0;
+        for (int i = 0; i < s.n; ++i) {
+            const int per = record_rows_per_wave(s.m[i].occ, s.m[i].nx);
+            r.m[i].begin = waves;
+            waves += (s.m[i].ny * s.m[i].nz + per - 1) / per;
+        }
+        r.total = waves;
+        hipLaunchKernelGGL(k_row_records, dim3((waves + 3) / 4), dim3(256), 0, st, r);
+        int rc = check_launch("k_row_records");
+        if (rc) return rc;
+        static bool done_rows = false;
+        rc = allow_lds(k_edt_xy_rows<TW, WIDE, NTX>, done_rows);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_edt_xy_rows<TW, WIDE, NTX>), dim3(s.total), dim3(NTX),
+                           xy_rows_lds(TW, s.ny_max, NTX), st, s);
+        return check_launch("k_edt_xy_rows");
+    }
     static bool done = false;
     int rc = allow_lds(k_edt_xy<TW, WIDE, NTX>, done);
     if (rc) return rc;
@@ -265,10 +325,10 @@ edt_batch_map_t one_map(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, in
 }
 }  // namespace
 
-int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, uint32_t* xy, int tw, int nt,
+int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, uint32_t* xy, int tw, int nt,
                   hipStream_t st, const int* gate)
 {
-    const edt_batch_map_t m = one_map(g, occ, nullptr, reinterpret_cast<int32_t*>(xy));
+    const edt_batch_map_t m = one_map(g, occ, d2, reinterpret_cast<int32_t*>(xy));
     EdtMapSet s;
     fill_set(&m, 1, tw, false, s);
     s.gate = gate;

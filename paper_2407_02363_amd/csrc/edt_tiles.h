@@ -532,6 +532,69 @@ __host__ __device__ inline size_t xy_lds(int tw, int nyv, int nt = NT)
 }
 
 // One xy tile: slice z, columns [x0, x0 + TW), T = z * ntx + x0 / TW.
+// Steps 2-3 of one xy tile from its row records: per row y of slice z, the
+// tile's 64-bit occupancy word rword[y] (columns [64 w0, 64 w0 + 64)) and the
+// nearest occupied column left (rleft) and right (rright) of that word, -1
+// if none.  Writes the 2D site of every voxel of the tile.
+template <int TW, bool WIDE, int NTX>
+__device__ __forceinline__ void xy_bands(uint32_t* ent, const uint64_t* rword, const int16_t* rleft,
+                                         const int16_t* rright, uint32_t* __restrict__ xy, int nx,
+                                         int ny, int z, int x0, int w0, int L)
+{
+    constexpr int NB = NTX / TW;
+    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_prv[NB * TW];
+    const BandMeta meta{s_lo, s_hi, s_nxt, s_prv};
+
+    // ---- step 2, band-local: x' per row from the row records, then push
+    const int col = threadIdx.x % TW;
+    const int band = band_of<TW>();
+    const int xc = x0 + col;
+    const bool live = xc < nx;
+    const KeyY key{xc};
+    const int q0 = band * L;
+    const int q1 = min(ny, q0 + L);
+    {
+        const int bit = (x0 & 63) + col;
+        const uint64_t lmask = (2ull << bit) - 1ull;
+        const uint64_t rmask = ~0ull << bit;
+        BandStack<TW, WIDE, KeyY> st{ent + q0 * TW + col, 0, 0, 0, 0, 0};
+        if (live) {
+            for (int y = q0; y < q1; ++y) {
+                const uint64_t mk = rword[y];
+                const uint64_t lm = mk & lmask, rm = mk & rmask;
+                const int xl = lm ? (w0 * 64 + 63 - __clzll(lm)) : (int)rleft[y];
+                const int xr = rm ? (w0 * 64 + __ffsll((unsigned long long)rm) - 1) : (int)rright[y];
+                int xp;
+                if (xl < 0) xp = xr;
+                else if (xr < 0) xp = xl;
+                else xp = (xc - xl <= xr - xc) ? xl : xr;
+                if (xp < 0) continue;
+                const int d = xc - xp;
+                st.push((uint32_t)y | ((uint32_t)xp << 10), y, mul24(d, d) + mul24(y, y), key);
+            }
+        }
+        s_lo[band * TW + col] = 0;
+        s_hi[band * TW + col] = (int16_t)st.top;
+    }
+    __syncthreads();
+    merge_all<TW, NB, WIDE>(ent, L, col, band, live, meta, key);
+
+    // ---- step 3: every row of the band
+    if (!live || q0 >= q1) return;
+    // band-wide row pointer (scalar when a wave is one band); the lane adds its column
+    uint32_t* row = xy + ((size_t)z * ny + q0) * nx + x0;
+    uint32_t val = 0;
+    query_band<TW, NB>(
+        ent, L, col, meta, q0, q1, key,
+        [&](int, uint32_t e, int, int) { val = (e >> 10) | ((e & POS_MASK) << 16); },
+        [&](int) {
+            row[col] = val;
+            row += nx;
+        },
+        [&](int a, int b) {
+            for (int q = a; q < b; ++q, row += nx) row[col] = XY_NONE;
+        });}
+
 template <int TW, bool WIDE, int NTX = NT>
 __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
                                             uint32_t* __restrict__ xy, int nx, int ny, int nz,
@@ -547,9 +610,6 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
     uint64_t* rword = reinterpret_cast<uint64_t*>(lds + ent_words);     // [ny]
     int16_t* rleft = reinterpret_cast<int16_t*>(rword + ny);            // [ny]
     int16_t* rright = rleft + ny;                                       // [ny]
-    __shared__ int16_t s_lo[NB * TW], s_hi[NB * TW], s_nxt[NB * TW], s_prv[NB * TW];
-    const BandMeta meta{s_lo, s_hi, s_nxt, s_prv};
-
     const int z = T / ntx;
     const int x0 = (T - z * ntx) * TW;
     const int w0 = x0 >> 6;
@@ -645,55 +705,202 @@ __device__ __forceinline__ void edt_xy_tile(const uint8_t* __restrict__ occ,
         }
     }
 
-    // ---- step 2, band-local: x' per row from the row records, then push
-    const int col = threadIdx.x % TW;
-    const int band = band_of<TW>();
-    const int xc = x0 + col;
-    const bool live = xc < nx;
-    const KeyY key{xc};
-    const int q0 = band * L;
-    const int q1 = min(ny, q0 + L);
+    xy_bands<TW, WIDE, NTX>(ent, rword, rleft, rright, xy, nx, ny, z, x0, w0, L);
+}
+
+// ---------------------------------------------------------------------------
+// step 1 once per row, then steps 2-3 per (slice, column tile)
+// ---------------------------------------------------------------------------
+// Row records of a whole map, for rows of at least 64 voxels: per row (z, y)
+// and 64-column word w, the word (bit i = column 64 w + i occupied) and the
+// nearest occupied column left and right of it (-1 if none).  They live in
+// the d2 buffer, which the xy pass does not use and the z pass overwrites:
+// 12 bytes per word against 4 * 64 bytes of d2 per word, from the first
+// 8-byte boundary of d2 on.
+struct RowRecords {
+    uint64_t* word;
+    int16_t* left;
+    int16_t* right;
+};
+
+__host__ __device__ inline RowRecords row_records(int32_t* d2, int nx, int ny, int nz)
+{
+    const size_t rows = (size_t)ny * nz;
+    const size_t nw = (size_t)((nx + 63) >> 6);
+    const uintptr_t base = ((uintptr_t)d2 + 7) & ~(uintptr_t)7;
+    RowRecords r;
+    r.word = reinterpret_cast<uint64_t*>(base);
+    r.left = reinterpret_cast<int16_t*>(r.word + rows * nw);
+    r.right = r.left + rows * nw;
+    return r;
+}
+
+// Rows read 4 bytes per lane: rows of a multiple of 4 bytes from a 4-byte
+// aligned occupancy buffer.
+__host__ __device__ inline bool record_words(const void* occ, int nx)
+{
+    return ((uintptr_t)occ & 3u) == 0 && (nx & 3) == 0;
+}
+
+// Rows per wave for the row records: whole rows, at most 16 loads per lane
+// and (4 bytes per lane) 64 words per wave.
+__host__ __device__ inline int record_rows_per_wave(const void* occ, int nx)
+{
+    const int nw = (nx + 63) >> 6, nch = (nx + 255) >> 8;
+    if (!record_words(occ, nx)) return 16 / nw;
+    const int a = 64 / nw, b = 16 / nch;
+    return a < b ? a : b;
+}
+
+// Bits 0-15 of x spread to bits 0, 4, 8, ..., 60.
+__device__ __forceinline__ uint64_t spread4(uint64_t x)
+{
+    x &= 0xFFFFull;
+    x = (x | (x << 24)) & 0x000000FF000000FFull;
+    x = (x | (x << 12)) & 0x000F000F000F000Full;
+    x = (x | (x << 6)) & 0x0303030303030303ull;
+    x = (x | (x << 3)) & 0x1111111111111111ull;
+    return x;
+}
+
+// Every word's nearest occupied columns outside it within its row, for the
+// words held by lanes [0, items), nw lanes per row, and the stores.
+__device__ __forceinline__ void row_records_store(uint64_t mine, int items, int nw, size_t row0,
+                                                  const RowRecords& rec)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t filled = __ballot(lane < items && mine != 0);
+    const int rr = lane / nw;
+    const int s0 = rr * nw, e0 = s0 + nw;          // the lanes of this lane's row
+    const uint64_t lanes_below = ((1ull << lane) - 1ull) & ~((1ull << s0) - 1ull);
+    const uint64_t lanes_above =
+        (lane < 63 ? ~0ull << (lane + 1) : 0ull) & (e0 < 64 ? (1ull << e0) - 1ull : ~0ull);
+    const uint64_t below = filled & lanes_below;
+    const uint64_t above = filled & lanes_above;
+    const int pw = below ? 63 - __clzll(below) : 0;
+    const int qw = above ? __ffsll((unsigned long long)above) - 1 : 0;
+    const uint64_t wl = __shfl(mine, pw);
+    const uint64_t wr = __shfl(mine, qw);
+    if (lane < items) {
+        const size_t i = row0 * (size_t)nw + lane;
+        rec.word[i] = mine;
+        rec.left[i] = (int16_t)(below ? 64 * (pw - s0) + 63 - __clzll(wl) : -1);
+        rec.right[i] = (int16_t)(above ? 64 * (qw - s0) + __ffsll((unsigned long long)wr) - 1 : -1);
+    }
+}
+
+// The records of rows [row0, row0 + nrows), 4 bytes per lane: load j is the
+// 256 bytes (four words) of chunk j % nch of row j / nch; one ballot per byte
+// position gives, for each word of the chunk, every fourth bit.  Lane
+// r * nw + w keeps the four ballots of its load and interleaves them into
+// word w of row r.
+__device__ __forceinline__ void row_summary_words(const uint8_t* __restrict__ occ, int nx, size_t row0,
+                                                  int nrows, const RowRecords& rec)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int nw = (nx + 63) >> 6, nch = (nx + 255) >> 8;
+    const int loads = nrows * nch;      // <= 16
+    uint32_t v[16];
     {
-        const int bit = (x0 & 63) + col;
-        const uint64_t lmask = (2ull << bit) - 1ull;
-        const uint64_t rmask = ~0ull << bit;
-        BandStack<TW, WIDE, KeyY> st{ent + q0 * TW + col, 0, 0, 0, 0, 0};
-        if (live) {
-            for (int y = q0; y < q1; ++y) {
-                const uint64_t mk = rword[y];
-                const uint64_t lm = mk & lmask, rm = mk & rmask;
-                const int xl = lm ? (w0 * 64 + 63 - __clzll(lm)) : (int)rleft[y];
-                const int xr = rm ? (w0 * 64 + __ffsll((unsigned long long)rm) - 1) : (int)rright[y];
-                int xp;
-                if (xl < 0) xp = xr;
-                else if (xr < 0) xp = xl;
-                else xp = (xc - xl <= xr - xc) ? xl : xr;
-                if (xp < 0) continue;
-                const int d = xc - xp;
-                st.push((uint32_t)y | ((uint32_t)xp << 10), y, mul24(d, d) + mul24(y, y), key);
+        int rr = 0, k = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int x = 256 * k + 4 * lane;
+            v[j] = (j < loads && x < nx)
+                       ? *reinterpret_cast<const uint32_t*>(occ + (row0 + rr) * (size_t)nx + x)
+                       : 0u;
+            if (++k == nch) {
+                k = 0;
+                ++rr;
             }
         }
-        s_lo[band * TW + col] = 0;
-        s_hi[band * TW + col] = (int16_t)st.top;
+    }
+    // lane r * nw + w holds word w of row r: load (r * nch + w / 4), quarter w % 4
+    const int items = nrows * nw;
+    const int wr_ = lane % nw;
+    const int mine_load = lane < items ? (lane / nw) * nch + wr_ / 4 : -1;
+    uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint64_t m0 = __ballot((v[j] & 0x000000FFu) != 0), m1 = __ballot((v[j] & 0x0000FF00u) != 0);
+        const uint64_t m2 = __ballot((v[j] & 0x00FF0000u) != 0), m3 = __ballot((v[j] & 0xFF000000u) != 0);
+        if (j == mine_load) {
+            a0 = m0;
+            a1 = m1;
+            a2 = m2;
+            a3 = m3;
+        }
+    }
+    const int sh = 16 * (wr_ & 3);
+    const uint64_t mine = spread4(a0 >> sh) | (spread4(a1 >> sh) << 1) | (spread4(a2 >> sh) << 2) |
+                          (spread4(a3 >> sh) << 3);
+    row_records_store(mine, items, nw, row0, rec);
+}
+
+// The records of rows [row0, row0 + nrows) of one map by one wave, nrows <=
+// record_rows_per_wave(nx).  Item j (row j / nw, word j % nw) is the 64
+// consecutive bytes one byte per lane; all loads are issued first, then one
+// ballot per item gives its word, kept by lane j.  A ballot of the non-empty
+// words and two shuffles give every word's nearest occupied columns outside
+// it within its row.
+__device__ __forceinline__ void row_summary(const uint8_t* __restrict__ occ, int nx, size_t row0,
+                                            int nrows, const RowRecords& rec)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int nw = (nx + 63) >> 6;      // 1..16
+    const int items = nrows * nw;       // <= 16
+    uint8_t b[16];
+    {
+        int rr = 0, c = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int x = 64 * c + lane;
+            b[j] = (j < items && x < nx) ? occ[(row0 + rr) * (size_t)nx + x] : (uint8_t)0;
+            if (++c == nw) {
+                c = 0;
+                ++rr;
+            }
+        }
+    }
+    uint64_t mine = 0;                  // lane j keeps item j's word
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint64_t w = __ballot(b[j] != 0);
+        if (lane == j) mine = w;
+    }
+    row_records_store(mine, items, nw, row0, rec);
+}
+
+// Dynamic LDS of the xy tile that reads row records: envelope entries plus
+// the three row-record arrays.
+__host__ __device__ inline size_t xy_rows_lds(int tw, int nyv, int nt = NT)
+{
+    return (size_t)4 * nt * ((nyv + nt / tw - 1) / (nt / tw)) + 12 * (size_t)nyv;
+}
+
+// One xy tile (slice z, columns [x0, x0 + TW)) from the map's row records.
+template <int TW, bool WIDE, int NTX = NT>
+__device__ __forceinline__ void edt_xy_tile_rows(const RowRecords& rec, uint32_t* __restrict__ xy,
+                                                 int nx, int ny, int ntx, int T, uint32_t* lds)
+{
+    constexpr int NB = NTX / TW;
+    const int L = (ny + NB - 1) / NB;
+    uint32_t* ent = lds;                                                  // [NB*L][TW]
+    uint64_t* rword = reinterpret_cast<uint64_t*>(lds + NB * L * TW);     // [ny]
+    int16_t* rleft = reinterpret_cast<int16_t*>(rword + ny);              // [ny]
+    int16_t* rright = rleft + ny;                                         // [ny]
+    const int z = T / ntx;
+    const int x0 = (T - z * ntx) * TW;
+    const int w0 = x0 >> 6;
+    const int nw = (nx + 63) >> 6;
+    for (int y = threadIdx.x; y < ny; y += NTX) {
+        const size_t i = ((size_t)z * ny + y) * nw + w0;
+        rword[y] = rec.word[i];
+        rleft[y] = rec.left[i];
+        rright[y] = rec.right[i];
     }
     __syncthreads();
-    merge_all<TW, NB, WIDE>(ent, L, col, band, live, meta, key);
-
-    // ---- step 3: every row of the band
-    if (!live || q0 >= q1) return;
-    // band-wide row pointer (scalar when a wave is one band); the lane adds its column
-    uint32_t* row = xy + ((size_t)z * ny + q0) * nx + x0;
-    uint32_t val = 0;
-    query_band<TW, NB>(
-        ent, L, col, meta, q0, q1, key,
-        [&](int, uint32_t e, int, int) { val = (e >> 10) | ((e & POS_MASK) << 16); },
-        [&](int) {
-            row[col] = val;
-            row += nx;
-        },
-        [&](int a, int b) {
-            for (int q = a; q < b; ++q, row += nx) row[col] = XY_NONE;
-        });
+    xy_bands<TW, WIDE, NTX>(ent, rword, rleft, rright, xy, nx, ny, z, x0, w0, L);
 }
 
 // ---------------------------------------------------------------------------

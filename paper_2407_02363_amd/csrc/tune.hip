@@ -37,10 +37,10 @@ int time_pass(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, int32_t* sit
     for (int r = 0; r <= reps && !rc; ++r) {
         // the z pass consumes its input in place: give it a fresh xy result
         if (pass == 2)
-            rc = launch_edt_xy(g, occ, reinterpret_cast<uint32_t*>(site), prep.xy_tw, prep.xy_nt, st);
+            rc = launch_edt_xy(g, occ, d2, reinterpret_cast<uint32_t*>(site), prep.xy_tw, prep.xy_nt, st);
         if (rc) break;
         (void)hipEventRecord(a, st);
-        rc = pass == 1 ? launch_edt_xy(g, occ, reinterpret_cast<uint32_t*>(site), tw, nt, st)
+        rc = pass == 1 ? launch_edt_xy(g, occ, d2, reinterpret_cast<uint32_t*>(site), tw, nt, st)
                        : launch_edt_z(g, d2, site, tw, nt, st);
         (void)hipEventRecord(b, st);
         if (rc) break;
@@ -128,7 +128,7 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
         g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz, bnt, bxnt};
     }
     // leave a complete transform in d2 / site
-    rc = launch_edt_xy(grid, occ, reinterpret_cast<uint32_t*>(site), bxy, bxnt, st);
+    rc = launch_edt_xy(grid, occ, d2, reinterpret_cast<uint32_t*>(site), bxy, bxnt, st);
     if (!rc) rc = launch_edt_z(grid, d2, site, bz, bnt, st);
     if (rc) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) {
