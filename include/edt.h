@@ -294,7 +294,7 @@ int edt_compute_tuned(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, i
  * callers that pipeline the passes of several maps.
  *   stage EDT_STAGE_XY: steps 1-3 of Sec. III-C in every z slice; writes the
  *         2D nearest site of each voxel, packed x' | y' << 16 (0xFFFFFFFF if
- *         the slice is empty), into site.  With nx >= 64 it first writes
+ *         the slice is empty), into site.  With nx >= 256 it first writes
  *         per-row records of step 1 (12 bytes per 64 columns) into d2, as
  *         scratch; d2 holds nothing meaningful after this stage.
  *   stage EDT_STAGE_Z: step 4 (steps 2-3 along z); reads that packed form

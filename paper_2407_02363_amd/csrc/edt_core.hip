@@ -93,12 +93,14 @@ int allow_lds(K kernel, bool& done)
     return EDT_OK;
 }
 
-// Step 1 once per row when every map's rows are at least 64 voxels long (so
-// the records fit in its d2 buffer), else inside every tile from the slice.
+// Step 1 once per row when every map's rows are at least 256 voxels long,
+// else inside every tile from the slice.  The records need rows of 64 or more
+// to fit in d2; below 256 a slice is staged by few tiles, and the extra
+// kernel costs more than the staging it saves (measured on maps of 64-256).
 bool rows_first(const EdtMapSet& s)
 {
     for (int i = 0; i < s.n; ++i)
-        if (s.m[i].nx < 64 || !s.m[i].d2) return false;
+        if (s.m[i].nx < 256 || !s.m[i].d2) return false;
     return true;
 }
 

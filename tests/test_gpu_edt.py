@@ -43,6 +43,8 @@ SHAPES = [
     (20, 520, 33),       # ny > 512: 16-wide xy tiles, 64-bit envelope test
     (700, 9, 11),        # nz > 512: 8-wide z tiles, 64-bit envelope test
     (7, 6, 1000),        # nx > 512: many words per row, 64-bit envelope test
+    (6, 40, 301),        # row records read byte by byte (nx >= 256, not a multiple of 4)
+    (5, 33, 300),        # row records read 4 bytes per lane, last 256-byte chunk partial
 ]
 
 
