@@ -30,13 +30,18 @@
 // keep packed self-contained entries (position | x' << 10 [| y' << 20]), so a
 // key is recomputed from an entry and no side table is needed.
 //
-//   xy tile   work-group = (z slice, TW consecutive columns).  The slice
-//             arrives as 16-byte loads turned into a bit string in LDS; one
-//             thread per row cuts out the tile's 64-bit word plus the
-//             nearest set bit left and right of it; the (column, band)
-//             threads derive x' per row from those and feed their stacks.
-//             Output: the 2D site x' | y' << 16 of every voxel, written into
-//             the site buffer (0xFFFFFFFF if the slice is empty).
+//   row records  one wave per group of whole rows (rows of 256 voxels or
+//             more): per 64-column word, the word and the nearest occupied
+//             column left and right of it, from ballots over the row's
+//             bytes, written into the d2 buffer as scratch.
+//   xy tile   work-group = (z slice, TW consecutive columns).  Per row, the
+//             tile's 64-bit word plus the nearest set bit left and right of
+//             it: read from the row records, or (narrower rows, and the
+//             persistent batched kernel) cut out of the slice staged in LDS
+//             as a bit string from 16-byte loads.  The (column, band) threads
+//             derive x' per row from those and feed their stacks.  Output:
+//             the 2D site x' | y' << 16 of every voxel, written into the site
+//             buffer (0xFFFFFFFF if the slice is empty).
 //   z tile    work-group = (row y, TW consecutive columns), all z.  Threads
 //             load their band of the packed 2D sites (coalesced along x),
 //             build, merge, query and overwrite d2 and site in place: every
