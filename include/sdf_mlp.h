@@ -8,7 +8,8 @@
  * such network: the exact self-map EDT (edt.h) produces its training labels,
  * stays the fallback for every state whose prediction lies within the
  * safety margin plus the network's measured error bound (per sphere, from
- * held-out states: sdf_mlp_calibrate), and is the judge of that error.
+ * held-out states: sdf_mlp_calibrate), and is what that error is measured
+ * against.
  *
  * Network: input [sin q1, cos q1, ..., sin q7, cos q7] -> 256 -> 256 -> 256
  * -> 12, ReLU between layers.  BF16 inputs, weights and hidden activations

@@ -10,8 +10,9 @@ whole chunk is
 replayed from a HIP graph whose pose and centre buffers are refilled before
 every replay.  Graphs exist for chunk sizes 1, 2, 4, ... and the full
 chunk, so a partial chunk (the states the surrogate could not clear, for
-instance) costs the next size up rather than a full chunk.  These distances are the surrogate's labels and the judge of
-its error; the same path is the fallback when the surrogate is not trusted.
+instance) costs the next size up rather than a full chunk.  These distances are the
+surrogate's labels and the measure of its error; the same path is the
+fallback when the surrogate is not trusted.
 Only orchestration lives here.
 """
 from __future__ import annotations
