@@ -128,11 +128,11 @@ struct BandStack {
             --top;
             pb = pa;
             kb = ka;
-            if (top >= 2) {
-                const uint32_t ea = slot[(top - 2) * TW];
-                pa = (int)(ea & POS_MASK);
-                ka = key(ea);
-            }
+            // the new second entry; with fewer than two left the value is
+            // read from slot 0 and never used (one branch less per pop)
+            const uint32_t ea = slot[(top >= 2 ? top - 2 : 0) * TW];
+            pa = (int)(ea & POS_MASK);
+            ka = key(ea);
         }
         slot[top * TW] = e;
         ++top;
