@@ -465,34 +465,36 @@ __device__ __forceinline__ void query_band(const uint32_t* ent, int L, int col, 
     }
     uint32_t ek = E(j, k);
     int pk = (int)(ek & POS_MASK), kk = key(ek);
-    int hij = HI(j);
+    // the current band's end and where the envelope goes on after it, kept
+    // in registers and refreshed only when the march changes band
+    int hij = HI(j), jnx = NX(j);
+    int lonx = jnx < NB ? LO(jnx) : 0;
     // next site and the running test value g(q) = q * dp2 - dK (advance iff g > 0)
     int jn = 0, kn = 0, pn = 0, kkn = 0, dp2 = 0, g = 0;
     uint32_t en = 0;
     bool has_next = false;
     auto load_next = [&](int q) {
-        if (k + 1 < hij) {
-            jn = j;
-            kn = k + 1;
-        } else {
-            jn = NX(j);
-            kn = jn < NB ? LO(jn) : 0;
-        }
+        const bool same = k + 1 < hij;
+        jn = same ? j : jnx;
+        kn = same ? k + 1 : lonx;
         has_next = jn < NB;
-        if (has_next) {
-            en = E(jn, kn);
-            pn = (int)(en & POS_MASK);
-            kkn = key(en);
-            dp2 = 2 * (pn - pk);
-            g = mul24(q, dp2) - (kkn - kk);
-        }
+        // past the column's last site, read the current one (value unused)
+        en = E(has_next ? jn : j, has_next ? kn : k);
+        pn = (int)(en & POS_MASK);
+        kkn = key(en);
+        dp2 = 2 * (pn - pk);
+        g = mul24(q, dp2) - (kkn - kk);
     };
     load_next(q0);
     begin(q0, ek, pk, kk);
     for (int q = q0; q < q1; ++q) {
         if (has_next && g > 0) {
             do {
-                if (jn != j) hij = HI(jn);
+                if (jn != j) {
+                    hij = HI(jn);
+                    jnx = NX(jn);
+                    lonx = jnx < NB ? LO(jnx) : 0;
+                }
                 j = jn;
                 k = kn;
                 ek = en;
