@@ -162,7 +162,7 @@ template <int TW, bool WIDE, class KeyF>
 __device__ void merge_group(const uint32_t* ent, int L, int col, const BandMeta& m, const KeyF& key,
                             int gl, int gm, int gr)
 {
-    auto E = [&](int b, int i) { return ent[(b * L + i) * TW + col]; };
+    auto E = [&](int b, int i) { return ent[(mul24(b, L) + i) * TW + col]; };
     auto LO = [&](int b) -> int16_t& { return m.lo[b * TW + col]; };
     auto HI = [&](int b) -> int16_t& { return m.hi[b * TW + col]; };
     int lastL = gm - 1;
@@ -281,7 +281,7 @@ template <int TW, int G, bool WIDE, class KeyF>
 __device__ void stitch_bands(const uint32_t* ent, int L, int col, const BandMeta& m, const KeyF& key,
                              int b0)
 {
-    auto E = [&](int b, int i) { return ent[(b * L + i) * TW + col]; };
+    auto E = [&](int b, int i) { return ent[(mul24(b, L) + i) * TW + col]; };
     auto LO = [&](int b) -> int16_t& { return m.lo[b * TW + col]; };
     auto HI = [&](int b) -> int16_t& { return m.hi[b * TW + col]; };
     // last non-empty band before b (exists whenever the chain holds a site there)
@@ -416,7 +416,7 @@ __device__ __forceinline__ void query_band(const uint32_t* ent, int L, int col, 
                                            int q0, int q1, const KeyF& key, Begin begin, Step step,
                                            None none)
 {
-    auto E = [&](int b, int i) { return ent[(b * L + i) * TW + col]; };
+    auto E = [&](int b, int i) { return ent[(mul24(b, L) + i) * TW + col]; };
     auto LO = [&](int b) -> int { return m.lo[b * TW + col]; };
     auto HI = [&](int b) -> int { return m.hi[b * TW + col]; };
     auto NX = [&](int b) -> int { return m.nxt[b * TW + col]; };
