@@ -1,9 +1,11 @@
 // The exact squared EDT on gfx950 for one map: the xy-tile kernel (steps 1-3
 // of Sec. III-C in every slice) and the z-tile kernel (step 4), their
-// launchers and the tile heuristics.  The tile code is in edt_tiles.h.
+// launchers and the tile heuristics.  The tile code is in edt_tiles.h (every
+// shape and tiling) and edt_lean.h (the 64-column tiles of maps up to 256 rows
+// and 128 slices).
 #include <algorithm>
 
-#include "edt_tiles.h"
+#include "edt_lean.h"
 
 namespace edtmi {
 
@@ -77,6 +79,25 @@ __global__ __launch_bounds__(NTZ) void k_edt_z(EdtMapSet s)
     edt_z_tile<TW, WIDE, NTZ>(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, lds);
 }
 
+// Lean tiles (edt_lean.h): 64 columns, one wave per band.
+__global__ __launch_bounds__(256) void k_edt_z_lean(EdtMapSet s)
+{
+    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
+    const int T = (int)blockIdx.x;
+    const EdtMap& d = s.m[map_of(s, T)];
+    lean::z_tile(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin);
+}
+
+__global__ __launch_bounds__(512) void k_edt_xy_lean(EdtMapSet s)
+{
+    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
+    // as in k_edt_xy: chunks of 16 tiles per XCD, rotating over the XCDs
+    const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
+    const EdtMap& d = s.m[map_of(s, T)];
+    lean::xy_tile(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny,
+                  d.ntx, T - d.begin);
+}
+
 // Allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per
 // work-group); once per kernel instantiation.
 template <typename K>
@@ -104,21 +125,46 @@ bool rows_first(const EdtMapSet& s)
     return true;
 }
 
+// The lean tiles take maps with every axis <= 512 (24-bit arithmetic), up to
+// 256 rows (xy) or 128 slices (z), and rows of 64 voxels or more (the row
+// records must fit into d2).
+bool lean_xy_ok(const EdtMapSet& s)
+{
+    if (s.wide) return false;
+    for (int i = 0; i < s.n; ++i)
+        if (s.m[i].ny > lean::XY_MAX || s.m[i].nx < 64 || !s.m[i].d2) return false;
+    return true;
+}
+
+bool lean_z_ok(const EdtMapSet& s) { return !s.wide && s.nz_max <= lean::Z_MAX; }
+
+// Step 1 of every map of the set once per row, into the maps' d2 buffers.
+int launch_row_records(const EdtMapSet& s, hipStream_t st)
+{
+    static thread_local EdtMapSet r;   // the maps counted in waves (2.3 KiB: off the stack)
+    r = s;
+    int waves = 0;
+    for (int i = 0; i < s.n; ++i) {
+        const int per = record_rows_per_wave(s.m[i].occ, s.m[i].nx);
+        r.m[i].begin = waves;
+        waves += (s.m[i].ny * s.m[i].nz + per - 1) / per;
+    }
+    r.total = waves;
+    hipLaunchKernelGGL(k_row_records, dim3((waves + 3) / 4), dim3(256), 0, st, r);
+    return check_launch("k_row_records");
+}
+
 template <int TW, bool WIDE, int NTX>
 int launch_xy_w(const EdtMapSet& s, hipStream_t st)
 {
+    if (TW == 64 && NTX == 512 && !WIDE && lean_xy_ok(s)) {
+        int rc = launch_row_records(s, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_edt_xy_lean, dim3(s.total), dim3(512), 0, st, s);
+        return check_launch("k_edt_xy_lean");
+    }
     if (rows_first(s)) {
-        static thread_local EdtMapSet r;   // the maps counted in waves (2.3 KiB: off the stack)
-        r = s;
-        int waves = 0;
-        for (int i = 0; i < s.n; ++i) {
-            const int per = record_rows_per_wave(s.m[i].occ, s.m[i].nx);
-            r.m[i].begin = waves;
-            waves += (s.m[i].ny * s.m[i].nz + per - 1) / per;
-        }
-        r.total = waves;
-        hipLaunchKernelGGL(k_row_records, dim3((waves + 3) / 4), dim3(256), 0, st, r);
-        int rc = check_launch("k_row_records");
+        int rc = launch_row_records(s, st);
         if (rc) return rc;
         static bool done_rows = false;
         rc = allow_lds(k_edt_xy_rows<TW, WIDE, NTX>, done_rows);
@@ -144,6 +190,10 @@ int launch_xy_tw(const EdtMapSet& s, hipStream_t st)
 template <int TW, bool WIDE, int NTZ>
 int launch_z_t(const EdtMapSet& s, hipStream_t st)
 {
+    if (TW == 64 && NTZ == 256 && !WIDE && lean_z_ok(s)) {
+        hipLaunchKernelGGL(k_edt_z_lean, dim3(s.total), dim3(64 * ((s.nz_max + 31) / 32)), 0, st, s);
+        return check_launch("k_edt_z_lean");
+    }
     static bool done = false;
     int rc = allow_lds(k_edt_z<TW, WIDE, NTZ>, done);
     if (rc) return rc;
@@ -217,6 +267,11 @@ EdtTuning default_tuning(const edt_grid_t* g)
     t.xy_nt = g->ny > 256 && g->ny <= 512 ? 512 : 256;
     t.z_tw = g->nz <= 128 ? 64 : (g->nz <= 256 ? 32 : 16);
     t.z_nt = 256;
+    // the lean tiles where they apply (64 / 512 for xy, 64 / 256 for z)
+    if (!needs_wide(g) && g->ny <= lean::XY_MAX && g->nx >= 64) {
+        t.xy_tw = 64;
+        t.xy_nt = 512;
+    }
     if (!tile_ok(1, t.xy_tw, g, t.xy_nt)) {
         t.xy_tw = 16;
         t.xy_nt = 256;

@@ -268,3 +268,27 @@ def test_cached_transform_skips_only_unchanged_maps(oracle_lib):
         d2.fill_(-5)
         edt.edt_compute_cached(g, o, d2, site, cache)   # a reset cache computes again
         check(*r2)
+
+
+LEAN_SHAPES = [(128, 64, 64), (97, 33, 65), (33, 256, 128), (32, 255, 200), (31, 1, 256), (64, 31, 127),
+               (96, 256, 64), (1, 40, 64), (128, 2, 300)]
+
+
+@pytest.mark.parametrize("shape", LEAN_SHAPES)
+def test_lean_tiles_sparse_slices_and_rows(oracle_lib, shape):
+    """Maps for the 64-column tiles (up to 128 slices and 256 rows): sites in a
+    few slices only (z bands with no site, one site, or a chain the seams
+    consume), sites in a few rows only (xy bands with 0-2 sites), and a dense
+    map (long pop chains)."""
+    nz, ny, nx = shape
+    g = np.random.Generator(np.random.PCG64(nz * 7 + ny * 3 + nx))
+    occ = np.zeros(shape, np.uint8)
+    for z in g.choice(nz, size=min(nz, 5), replace=False):
+        occ[z, g.integers(0, ny, 3), g.integers(0, nx, 3)] = 1
+    assert_same(occ, oracle_lib, "few slices")
+    occ = np.zeros(shape, np.uint8)
+    for z in range(nz):
+        for y in g.choice(ny, size=min(ny, 2), replace=False):
+            occ[z, y, g.integers(0, nx, 2)] = 1
+    assert_same(occ, oracle_lib, "few rows")
+    assert_same(inputs.random_grid(shape, 0.3, nz + ny + nx), oracle_lib, "dense")
