@@ -379,6 +379,25 @@ size_t edt_batch_workspace_bytes(int32_t n_maps);
 int edt_compute_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t ws_bytes,
                         const edt_tuning_t* tuning, void* stream);
 
+/*
+ * edt_compute_batched_noalloc -- edt_compute_batched for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and results, with the
+ * batch's workspace taken from a 256-byte array that the library holds on
+ * every GPU it runs on until the process ends.  The call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine.
+ *   maps, n_maps, tuning  as for edt_compute_batched (n_maps <= EDT_BATCH_MAX,
+ *           the limit of the array; more maps fail with EDT_ERR_ARG).
+ *   timed_out  nullable DEVICE int32: after the batch, 1 if a wait gave up
+ *           (as edt_batch_status reports), else 0; written in stream order.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (the call clears what must start at zero): calls that overlap on
+ * one GPU race.  The first call on a device looks up the array's address
+ * there (hipGetSymbolAddress); make it outside graph capture.
+ */
+int edt_compute_batched_noalloc(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuning_t* tuning,
+                                int32_t* timed_out, void* stream);
+
 /* Synchronises the stream and reports whether a batch launch that used ws
  * gave up waiting for a map's xy tiles (*timed_out = 1: that map's result
  * is incomplete).  Never expected; a guard against a stuck queue. */

@@ -51,6 +51,12 @@ __global__ void k_batch_reset(unsigned* ws, int n)
     if (i < n) ws[i] = 0u;
 }
 
+// The batch's flag of a wait that gave up, copied into a caller's int.
+__global__ void k_batch_flag_out(const unsigned* ws, int32_t* out)
+{
+    if (threadIdx.x == 0) *out = ws[WS_ERR] ? 1 : 0;
+}
+
 // At most 128 VGPRs, so that 4 waves fit per SIMD: the LDS of the larger
 // tiles allows 4 work-groups per CU, and the register allocator would
 // otherwise take more for the fused xy + z body than either part needs.
@@ -261,6 +267,43 @@ int batch_common(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t w
     return EDT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free batched launch: the same words as a
+// caller's workspace (queue head, error flag, one counter per map) for the
+// largest batch, held by every GPU the library runs on for the life of the
+// process.  Host code never passes the symbol itself to a kernel: it takes
+// the array's device address on each device once, with that device current.
+// ---------------------------------------------------------------------------
+constexpr int SCRATCH_WORDS = 64;
+static_assert(WS_DONE + EDT_BATCH_MAX <= SCRATCH_WORDS, "scratch too small for the largest batch");
+static __device__ __align__(256) unsigned scratch[SCRATCH_WORDS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of scratch on the current device (looked up once per device).
+int scratch_of_current_device(unsigned** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        set_error("edt_compute_batched_noalloc: no usable current device (%d)", dev);
+        return EDT_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("edt_compute_batched_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return EDT_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = static_cast<unsigned*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return EDT_OK;
+}
+
 }  // namespace
 
 }  // namespace edtmi
@@ -284,6 +327,23 @@ int edt_compute_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, s
     int rc = batch_common(maps, n_maps, ws, ws_bytes, tuning, p, t);
     if (rc) return rc;
     return launch_batched(p, t.xy_tw, t.z_tw, static_cast<unsigned*>(ws), as_stream(stream));
+}
+
+int edt_compute_batched_noalloc(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuning_t* tuning,
+                                int32_t* timed_out, void* stream)
+{
+    unsigned* ws = nullptr;
+    int rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    BatchPlan p;
+    EdtTuning t;
+    rc = batch_common(maps, n_maps, ws, (size_t)SCRATCH_WORDS * sizeof(unsigned), tuning, p, t);
+    if (rc) return rc;
+    const hipStream_t st = as_stream(stream);
+    rc = launch_batched(p, t.xy_tw, t.z_tw, ws, st);
+    if (rc || !timed_out) return rc;
+    hipLaunchKernelGGL(k_batch_flag_out, dim3(1), dim3(64), 0, st, ws, timed_out);
+    return check_launch("k_batch_flag_out");
 }
 
 int edt_batch_status(const void* ws, int32_t* timed_out, void* stream)

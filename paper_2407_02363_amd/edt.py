@@ -70,7 +70,7 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_update_logodds", "edt_outlier_workspace_bytes", "edt_outlier_filter",
             "edt_cache_workspace_bytes", "edt_cache_reset", "edt_compute_cached",
             "edt_jfa_workspace_bytes", "edt_jfa",
-            "edt_autotune_batched"]
+            "edt_autotune_batched", "edt_compute_batched_noalloc"]
 
 BATCH_MAX = 48
 
@@ -106,6 +106,7 @@ def lib():
         "edt_batch_workspace_bytes": ([i32], ctypes.c_size_t),
         "edt_compute_batched": ([P, i32, P, ctypes.c_size_t, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_compute_many": ([P, i32, ctypes.POINTER(Tuning), P], ctypes.c_int),
+        "edt_compute_batched_noalloc": ([P, i32, ctypes.POINTER(Tuning), P, P], ctypes.c_int),
         "edt_logodds_workspace_bytes": ([G], ctypes.c_size_t),
         "edt_logodds_reset": ([G, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_update_logodds": ([G, P, P, P, i64, P, P, P, ctypes.POINTER(LogOdds), P, ctypes.c_size_t,
@@ -317,6 +318,18 @@ def edt_compute_batched(maps, ws, tuning=None, stream=None):
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tuning(tuning),
                                      _stream(stream)),
            "edt_compute_batched")
+
+
+def edt_compute_batched_noalloc(maps, tuning=None, timed_out=None, stream=None):
+    """maps: result of batch_maps(); no workspace: the library's per-GPU
+    array serves the batch.  timed_out: optional int32 device tensor of one
+    element, set to 1 if a wait gave up."""
+    flag = None
+    if timed_out is not None:
+        flag = _dev(timed_out, torch.int32, "timed_out", 1)
+    _check(lib().edt_compute_batched_noalloc(ctypes.cast(maps, ctypes.c_void_p), len(maps),
+                                             _tuning(tuning), flag, _stream(stream)),
+           "edt_compute_batched_noalloc")
 
 
 def edt_batch_status(ws, stream=None) -> bool:
