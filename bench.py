@@ -9,17 +9,20 @@ in both.  Inputs are resident in device memory before timing starts.
 
 Printed as one JSON line:
   value        EDT voxels per second over whole cycles (2 maps per cycle),
-               in Mvoxels/s -- insert, clear and query time included; each
-               cycle runs the two maps on two streams from three HIP
-               graphs ("timing"); the eager one-stream rate is under
-               "eager" and the other ways of running it under
+               in Mvoxels/s -- insert, clear and query time included -- for
+               the fastest of the measured ways of running a cycle
+               ("timing"); every way, eager and graph-replayed, is under
                "cycle_variants".
   latency      p50 / p99 of the per-cycle latency over >= 1000 cycles, host
                clock from enqueue to the sphere results landing in host
                memory, plain per-map launches and graph-replayed cycles.
-  roofline     the dominant EDT kernel: algorithmic bytes / its average
-               duration (HIP events on its own stream) against 8 TB/s.
-  cpu_baseline the CPU oracle on a bounded sample of the same cycles.
+  roofline     the exact transform of one map (its kernels back to back):
+               the compulsory 9 bytes per voxel over its average duration
+               (HIP events on its own stream) against 8 TB/s; each kernel's
+               own figure under "kernels".
+  cpu_baseline the CPU oracle on a bounded sample of the same cycles, and
+               the oracle's transform alone on the control-cycle map and the
+               512^3 map with one thread and with every host thread.
 """
 from __future__ import annotations
 
@@ -43,6 +46,9 @@ METRIC = "EDT Mvoxels/s + % HBM roofline; p50/p99 insert→EDT→query cycle lat
 XY_BYTES_PER_VOXEL = 1 + 4      # occupancy byte in, packed 2D site out
 Z_BYTES_PER_VOXEL = 4 + 8       # packed 2D site in, d2 + site out
 EDT_BYTES_PER_VOXEL = 9         # compulsory: occupancy in, d2 + site out
+# the kernels of each pass on the control-cycle map (the lean 64-column tiles)
+XY_KERNELS = ["k_row_records", "k_edt_xy_lean"]
+Z_KERNELS = ["k_edt_z_lean"]
 
 
 # HBM traffic of the EDT kernels from hardware counters: a committed summary
@@ -51,7 +57,7 @@ EDT_BYTES_PER_VOXEL = 9         # compulsory: occupancy in, d2 + site out
 # only while the kernel sources hash to what they were when it was taken.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "edt_cycle256_pmc_traffic.md")
 EDT_KERNEL_SOURCES = ("paper_2407_02363_amd/csrc/common.h", "paper_2407_02363_amd/csrc/edt_tiles.h",
-                      "paper_2407_02363_amd/csrc/edt_core.hip")
+                      "paper_2407_02363_amd/csrc/edt_lean.h", "paper_2407_02363_amd/csrc/edt_core.hip")
 
 
 def edt_source_hash():
@@ -62,9 +68,10 @@ def edt_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of kernel on the control-cycle map, or None when
-    no counter summary exists for the current kernel sources."""
+def measured_traffic(kernels):
+    """HBM bytes per launch of the named kernels together on the
+    control-cycle map, or None when no counter summary exists for the
+    current kernel sources."""
     try:
         with open(TRAFFIC_PROFILE) as fh:
             text = fh.read()
@@ -76,8 +83,13 @@ def measured_traffic(kernel):
     d = json.loads(m.group(1))
     if d.get("source_sha256") != edt_source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["traffic_bytes_per_launch"])
+    total = 0.0
+    for kernel in kernels:
+        k = d.get("kernels", {}).get(kernel)
+        if k is None:
+            return None
+        total += float(k["traffic_bytes_per_launch"])
+    return total
 
 
 def log(*a):
@@ -134,13 +146,29 @@ def time_edt_kernels(edt, torch, grid, occ, d2, site, reps):
     return t_xy, t_pair - t_xy, t_all
 
 
-def cpu_baseline(ci, budget_s: float):
-    """Oracle cycles on the host until ~budget_s of CPU work is done."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ci, budget_s: float, large: bool = True):
+    """The oracle on the host: whole control cycles until ~budget_s of CPU
+    work is done (every host thread), and its transform alone on the
+    control-cycle environment map (median of 5) and the 512^3 blob map
+    (median of 3), with one thread and with every host thread."""
     import oracle
     from paper_2407_02363_amd import inputs
+    oracle.build(force=False)   # built -O3 -fopenmp, no FP contraction
     g = ci.grid
     n_cycles = 0
     t0 = time.perf_counter()
+    occ_env = None
     while True:
         k = n_cycles
         q = ci.joint_states[k % len(ci.joint_states)]
@@ -154,15 +182,43 @@ def cpu_baseline(ci, budget_s: float):
         C = inputs.sphere_centres(ci.robot, q, ci.sphere_links, ci.sphere_local)
         oracle.query_spheres(g, d2e, se, C, ci.sphere_radii)
         oracle.query_spheres(g, d2s, ss, C, ci.sphere_radii)
+        if occ_env is None:
+            occ_env = occ_e
         n_cycles += 1
         el = time.perf_counter() - t0
         if el >= budget_s and n_cycles >= 2:
             break
     vox = 2 * g.n * n_cycles
-    return {"value": vox / el / 1e6, "unit": "Mvoxels/s", "cores": oracle.max_threads(),
+    threads = oracle.max_threads()
+
+    def edt_median(occ, nthreads, runs):
+        ts = []
+        for _ in range(runs):
+            t = time.perf_counter()
+            oracle.edt(occ, nthreads)
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    edt_only = {}
+    maps = [("control_cycle_256x256x128", occ_env, 5)]
+    if large:
+        maps.append(("blobs_512^3", inputs.blobs_grid(512), 3))
+    for name, occ, runs in maps:
+        r = {"voxels": int(occ.size), "runs": runs}
+        # the oracle sets the thread count for the process: name it every time
+        for label, nt in (("1_thread", 1), ("all_threads", threads)):
+            t = edt_median(occ, nt, runs)
+            r[label] = {"ms": 1e3 * t, "mvox_s": occ.size / t / 1e6, "threads": nt}
+        edt_only[name] = r
+    oracle.edt(occ_env[:1], threads)   # leave every thread in use
+    return {"value": vox / el / 1e6, "unit": "Mvoxels/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{n_cycles} full control cycles (2 maps of 256x256x128 each) in {el:.1f} s",
-            "ms_per_cycle": 1e3 * el / n_cycles}
+            "sample": f"{n_cycles} full control cycles (2 maps of 256x256x128 each) in {el:.1f} s, "
+                      f"{threads} threads",
+            "ms_per_cycle": 1e3 * el / n_cycles,
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "threads": threads,
+            "build": "gcc -O3 -fopenmp -ffp-contract=off",
+            "edt_only": edt_only}
 
 
 def batched_workload(args, torch, edt, inputs, host_latency=True):
@@ -400,7 +456,7 @@ def large_map_workload(args, torch, edt, inputs):
            "tiles": list(edt.edt_default_tuning(g)),
            "edt_ms": t_all, "mvox_s": g.n / (t_all * 1e-3) / 1e6,
            "frac_9B": EDT_BYTES_PER_VOXEL * g.n / (t_all * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    for name, t, b in (("k_edt_xy", t_xy, XY_BYTES_PER_VOXEL), ("k_edt_z", t_z, Z_BYTES_PER_VOXEL)):
+    for name, t, b in (("xy_pass", t_xy, XY_BYTES_PER_VOXEL), ("z_pass", t_z, Z_BYTES_PER_VOXEL)):
         gbs = b * g.n / (t * 1e-3) / 1e9
         res[name] = {"avg_us": 1e3 * t, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
     del occ, d2, site
@@ -614,37 +670,75 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
-    # ---- throughput: K cycles back to back.  Eager: one library call per
-    # step of the cycle on one stream.  Headline: the two maps on two streams,
-    # each cycle replayed from three single-stream HIP graphs (self-map
-    # insertion; the whole environment map on a second stream; the self-map
-    # transform and query), so the two maps' kernels overlap.
-    log(f"[bench] timing {args.steps} eager cycles")
-    el_eager = run_steps(cyc.run, args.steps)
-    eager = {"ms_per_cycle": 1e3 * el_eager / args.steps,
-             "mvox_s": cyc.voxels_per_cycle * args.steps / el_eager / 1e6}
-    split = args.graphs > 0
-    if split:
+    ref = None
+
+    def check_same(cv, name):
+        cv.run(1)
+        torch.cuda.synchronize()
+        got = (cv.d2_env, cv.site_env, cv.d2_self, cv.site_self, cv.out_env, cv.out_self)
+        if not all(torch.equal(a, b) for a, b in zip(ref, got)):
+            raise SystemExit(f"cycle variant {name} differs from the eager one-stream cycle")
+
+    # ---- every way of running a cycle, K cycles back to back each (results
+    # checked bytewise against the eager one-stream cycle first):
+    #   per_map_one_stream   one library call per step, one stream
+    #   per_map_two_streams  the environment map on a second stream
+    #   many_one_stream      both maps' EDTs in one launch per pass
+    #   batched_persistent   both maps' EDTs in one persistent launch
+    #   ..._graph            the same cycle replayed from one HIP graph
+    #   split_graphs         two streams, three single-stream graphs per cycle
+    cyc.run(1)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (cyc.d2_env, cyc.site_env, cyc.d2_self, cyc.site_self, cyc.out_env,
+                               cyc.out_self)]
+    variants = {}
+    best = None   # (ms_per_cycle, name, voxels per cycle)
+    for name, kw in (("per_map_one_stream", {"edt_mode": "per_map"}),
+                     ("per_map_two_streams", {"edt_mode": "per_map", "two_streams": True}),
+                     ("many_one_stream", {"edt_mode": "many"}),
+                     ("batched_persistent", {"edt_mode": "batched"})):
+        log(f"[bench] cycle variant {name}")
+        cv = cyc if name == "per_map_one_stream" else ControlCycle(ci, dev, **kw)
+        for k in range(args.warmup):
+            cv.run(k)
+        check_same(cv, name)
+        el_v = run_steps(cv.run, args.steps)
+        r = {"eager_ms_per_cycle": 1e3 * el_v / args.steps,
+             "eager_mvox_s": cv.voxels_per_cycle * args.steps / el_v / 1e6}
+        cand = [(1e3 * el_v / args.steps, name, el_v)]
+        if args.graphs > 0:
+            gv = cv.capture_graphs(args.graphs)
+            for k in range(args.warmup):
+                gv[k % len(gv)].replay()
+            el_vg = run_steps(lambda k: gv[k % len(gv)].replay(), args.steps)
+            r.update({"graph_ms_per_cycle": 1e3 * el_vg / args.steps,
+                      "graph_mvox_s": cv.voxels_per_cycle * args.steps / el_vg / 1e6})
+            cand.append((1e3 * el_vg / args.steps, name + "_graph", el_vg))
+            del gv
+        variants[name] = r
+        for c in cand:
+            if best is None or c[0] < best[0]:
+                best = c
+        if cv is not cyc:
+            del cv
+    if args.graphs > 0:
         log(f"[bench] capturing {args.graphs} split cycle graphs")
         cyc.run(1)
         torch.cuda.synchronize()
-        ref = [t.clone() for t in (cyc.d2_env, cyc.site_env, cyc.d2_self, cyc.site_self,
-                                   cyc.out_env, cyc.out_self)]
         cyc.capture_split_graphs(args.graphs)
         cyc.replay_split(1)
         torch.cuda.synchronize()
-        if not all(torch.equal(a, b) for a, b in
-                   zip(ref, (cyc.d2_env, cyc.site_env, cyc.d2_self, cyc.site_self, cyc.out_env,
-                             cyc.out_self))):
+        got = (cyc.d2_env, cyc.site_env, cyc.d2_self, cyc.site_self, cyc.out_env, cyc.out_self)
+        if not all(torch.equal(a, b) for a, b in zip(ref, got)):
             raise SystemExit("split-graph replay differs from the eager cycle")
         for k in range(args.warmup):
             cyc.replay_split(k)
-        log(f"[bench] timing {args.steps} graph-replayed two-stream cycles")
-        el = run_steps(cyc.replay_split, args.steps)
-        mode = "two streams, three graphs per cycle"
-    else:
-        el, mode = el_eager, "eager, one stream"
-    ms_per_step = 1e3 * el / args.steps
+        el_s = run_steps(cyc.replay_split, args.steps)
+        variants["split_graphs"] = {"graph_ms_per_cycle": 1e3 * el_s / args.steps,
+                                    "graph_mvox_s": cyc.voxels_per_cycle * args.steps / el_s / 1e6}
+        if 1e3 * el_s / args.steps < best[0]:
+            best = (1e3 * el_s / args.steps, "split_graphs", el_s)
+    ms_per_step, mode, el = best
     value = cyc.voxels_per_cycle * args.steps / el / 1e6
 
     # ---- latency: enqueue -> results in host memory, per cycle
@@ -666,39 +760,20 @@ def main():
     lat_plain = latency_run(cyc.run, args.latency_cycles)
     latency = {"plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
                          "cycles": len(lat_plain)}}
-    if split:
+    if args.graphs > 0:
         lat_graph = latency_run(cyc.replay_split, args.latency_cycles)
         latency["graph"] = {"p50_ms": pct(lat_graph, 50), "p99_ms": pct(lat_graph, 99),
-                            "cycles": len(lat_graph)}
+                            "cycles": len(lat_graph), "schedule": "split_graphs"}
 
-    # ---- the same cycle with the EDTs run other ways (identical results)
-    variants = {}
-    for name, kw in (("many_one_stream", {"edt_mode": "many"}),
-                     ("per_map_one_stream", {"edt_mode": "per_map"}),
-                     ("per_map_two_streams", {"edt_mode": "per_map", "two_streams": True}),
-                     ("batched_persistent", {"edt_mode": "batched"})):
-        log(f"[bench] cycle variant {name}")
-        cv = ControlCycle(ci, dev, **kw)
-        for k in range(args.warmup):
-            cv.run(k)
-        cv.run(1)
-        cyc.run(1)
-        torch.cuda.synchronize()
-        if not all(torch.equal(a, b) for a, b in
-                   ((cv.d2_env, cyc.d2_env), (cv.site_env, cyc.site_env), (cv.d2_self, cyc.d2_self),
-                    (cv.site_self, cyc.site_self), (cv.out_env, cyc.out_env),
-                    (cv.out_self, cyc.out_self))):
-            raise SystemExit(f"cycle variant {name} differs from the default cycle")
-        el_v = run_steps(cv.run, args.steps)
-        r = {"eager_ms_per_cycle": 1e3 * el_v / args.steps}
-        if args.graphs > 0:
-            gv = cv.capture_graphs(args.graphs)
-            el_vg = run_steps(lambda k: gv[k % len(gv)].replay(), args.steps)
-            r.update({"graph_ms_per_cycle": 1e3 * el_vg / args.steps,
-                      "graph_mvox_s": cv.voxels_per_cycle * args.steps / el_vg / 1e6})
-            del gv
-        variants[name] = r
-        del cv
+    # ---- the host -> device upload of one frame, which a live sensor adds to
+    # every cycle (Alg. 2 inserts a new cloud each cycle): pinned host buffer
+    # to the device buffer the insertion reads
+    frame_host = torch.from_numpy(ci.frames[0]).pin_memory()
+    frame_dev = torch.empty(frame_host.shape, dtype=frame_host.dtype, device=dev)
+    t_h2d = time_median(torch, lambda: frame_dev.copy_(frame_host, non_blocking=True), 200)
+    h2d = {"bytes": int(frame_host.numel() * 4), "us": 1e3 * t_h2d,
+           "GBs": frame_host.numel() * 4 / (t_h2d * 1e-3) / 1e9,
+           "cycle_ms_with_upload": ms_per_step + t_h2d}
 
     # ---- per-kernel timing and roofline on the environment map
     log("[bench] per-kernel timing")
@@ -708,20 +783,23 @@ def main():
     t_xy, t_z, t_all = time_edt_kernels(edt, torch, g, occ, d2, site, args.kernel_reps)
     nvox = g.n
     kernels = {
-        "k_edt_xy": {"avg_us": 1e3 * t_xy, "bytes_per_voxel": XY_BYTES_PER_VOXEL},
-        "k_edt_z": {"avg_us": 1e3 * t_z, "bytes_per_voxel": Z_BYTES_PER_VOXEL},
+        "xy_pass": {"kernels": XY_KERNELS, "avg_us": 1e3 * t_xy, "bytes_per_voxel": XY_BYTES_PER_VOXEL},
+        "z_pass": {"kernels": Z_KERNELS, "avg_us": 1e3 * t_z, "bytes_per_voxel": Z_BYTES_PER_VOXEL},
     }
     for k in kernels.values():
         k["achieved_GBs"] = k["bytes_per_voxel"] * nvox / (k["avg_us"] * 1e-6) / 1e9
-    dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
-    kd = kernels[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBs"],
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["achieved_GBs"] / HBM_PEAK_GBS,
-                "traffic": measured_traffic(dom),
-                "algorithmic_bytes_per_launch": kd["bytes_per_voxel"] * nvox}
+        k["frac"] = k["achieved_GBs"] / HBM_PEAK_GBS
+        k["traffic"] = measured_traffic(k["kernels"])
     edt_alg = EDT_BYTES_PER_VOXEL * nvox / (t_all * 1e-3) / 1e9
     edt_only = {"avg_us": 1e3 * t_all, "mvox_s": nvox / (t_all * 1e-3) / 1e6,
-                "algorithmic_GBs_9B": edt_alg, "frac_9B": edt_alg / HBM_PEAK_GBS}
+                "algorithmic_GBs_9B": edt_alg, "frac_9B": edt_alg / HBM_PEAK_GBS,
+                "target_us_at_50pct": EDT_BYTES_PER_VOXEL * nvox / (0.5 * HBM_PEAK_GBS * 1e9) * 1e6}
+    roofline = {"bound": "hbm", "kernel": "xy+z (" + ", ".join(XY_KERNELS + Z_KERNELS) + ")",
+                "achieved": edt_alg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": edt_alg / HBM_PEAK_GBS,
+                "traffic": measured_traffic(XY_KERNELS + Z_KERNELS),
+                "algorithmic_bytes_per_launch": EDT_BYTES_PER_VOXEL * nvox,
+                "avg_us": 1e3 * t_all}
 
     log("[bench] probabilistic occupancy front end")
     occupancy = occupancy_workload(args, torch, edt, ci, cyc)
@@ -753,7 +831,7 @@ def main():
                       "grid": [g.nx, g.ny, g.nz], "maps_per_cycle": 2,
                       "points_per_frame": int(ci.frames[0].shape[0]),
                       "link_points": int(ci.link_pts.shape[0]), "spheres": int(cyc.radii.numel())},
-           "timing": mode, "eager": eager, "latency": latency,
+           "timing": mode, "latency": latency, "h2d_frame": h2d,
            "cycle_variants": variants, "occupancy": occupancy, "static_scene": static_scene,
            "edt_comparison": comparison, "closed_loop": closed_loop, "large_map": large_map,
            "edt_only": edt_only, "kernels": kernels, "roofline": roofline,

@@ -203,6 +203,10 @@ int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, c
  * neighbour search is exact for coordinates within about 80 m of the
  * sensor origin (cells of 1.001 radius).
  *   pts        device float32 [n][3], sensor frame; n <= EDT_OUTLIER_MAX_POINTS
+ *   radius     metres, > 0; n * radius^2 must stay below 32,000 m^2 (and
+ *              n * radius below 8e6 m) so that the exact sums cannot overflow
+ *              (at 307,200 points: radius below 0.32 m; at the maximum count
+ *              below 8.7 cm)
  *   k          1..16 neighbours
  *   keep       device uint8 [n] out
  *   mean_dist  device float32 [n] out (nullable): d_i, NaN for non-finite

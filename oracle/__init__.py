@@ -34,10 +34,10 @@ Q_EMPTY = 2
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (-O2, OpenMP, no FP contraction)."""
+    """Compile liboracle.so with gcc (-O3, OpenMP, no FP contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC",
                                "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

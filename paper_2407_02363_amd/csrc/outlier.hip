@@ -311,6 +311,9 @@ size_t edt_outlier_workspace_bytes(int64_t n_points)
     return sor_layout(n_points).total + (size_t)std::max<int64_t>(n_points, 1) * 4;
 }
 
+constexpr double OUTLIER_SUM2_MAX = 32000.0;     // m^2, below 2^15
+constexpr double OUTLIER_SUM1_MAX = 8000000.0;   // m, below 2^23
+
 int edt_outlier_filter(const float* pts, int64_t n, int32_t k, float radius, float alpha,
                        uint8_t* keep, float* mean_dist, double* stats, void* ws, size_t ws_bytes,
                        void* stream)
@@ -321,6 +324,16 @@ int edt_outlier_filter(const float* pts, int64_t n, int32_t k, float radius, flo
     }
     if (k < 1 || k > KMAX || !(radius > 0.0f) || !std::isfinite(radius) || !std::isfinite(alpha)) {
         set_error("edt_outlier_filter: need 1 <= k <= %d, a finite radius > 0 and a finite alpha", KMAX);
+        return EDT_ERR_ARG;
+    }
+    // every d_i is at most the radius, so the fixed-point sums (d_i in units
+    // of 2^-40, d_i^2 in units of 2^-48) stay below 2^63 while n * radius^2
+    // and n * radius stay below 2^15 m^2 and 2^23 m; a margin keeps rounding
+    // of the last unit inside
+    if ((double)n * (double)radius * (double)radius >= OUTLIER_SUM2_MAX ||
+        (double)n * (double)radius >= OUTLIER_SUM1_MAX) {
+        set_error("edt_outlier_filter: n * radius^2 = %g m^2 reaches %g (the exact sums would overflow)",
+                  (double)n * (double)radius * (double)radius, OUTLIER_SUM2_MAX);
         return EDT_ERR_ARG;
     }
     if (ws_bytes < edt_outlier_workspace_bytes(n)) {

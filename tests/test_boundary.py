@@ -118,6 +118,13 @@ def test_host_validation_rejects_bad_arguments(lib):
                                   None) == -1
     assert lib.edt_outlier_filter(one, 1000, 8, 0.01, 1.0, one, None, None, one, ow - 1, None) == -3
     assert lib.edt_outlier_filter(one, -1, 8, 0.01, 1.0, one, None, None, one, ow, None) == -1
+    # the exact fixed-point sums bound n * radius^2 (d_i <= radius)
+    owm = lib.edt_outlier_workspace_bytes(1_000_000)
+    assert lib.edt_outlier_filter(one, 1_000_000, 8, 0.2, 1.0, one, None, None, one, owm, None) == -1
+    assert b"overflow" in lib.edt_last_error()
+    ow4 = lib.edt_outlier_workspace_bytes(edt.OUTLIER_MAX_POINTS)
+    assert lib.edt_outlier_filter(one, edt.OUTLIER_MAX_POINTS, 8, 0.09, 1.0, one, None, None, one, ow4,
+                                  None) == -1
     # cached transform: cache size and NULLs before any launch
     cb = lib.edt_cache_workspace_bytes(ctypes.byref(ok))
     assert cb >= 256 + ok.nx * ok.ny * ok.nz

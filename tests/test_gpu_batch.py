@@ -204,14 +204,59 @@ def test_many_matches_oracle(oracle_lib, tiles):
     check(occs, d2s, sites, oracle_lib, f"many {tiles}")
 
 
-def test_many_equals_one_call_per_map():
-    """48 maps of one shape (the self-map labeler's case): identical to one
-    edt_compute per map."""
+def test_many_48_maps_of_one_shape(oracle_lib):
+    """48 maps of one shape (the self-map labeler's case), every map against
+    the oracle."""
     sh = (24, 40, 36)
     occs = [inputs.random_grid(sh, 0.003 * (1 + i % 5), 500 + i) for i in range(edt.BATCH_MAX)]
     grids = [inputs.Grid(sh[2], sh[1], sh[0])] * len(occs)
     d2s, sites = run_many(occs, grids)
-    from tests.gpu_util import gpu_edt
-    for i in (0, 1, 17, 47):
-        rd2, rs = gpu_edt(occs[i])
-        assert np.array_equal(d2s[i], rd2) and np.array_equal(sites[i], rs), i
+    check(occs, d2s, sites, oracle_lib, "48 maps")
+
+
+def test_batch_cycle_configured_size(oracle_lib):
+    """The batched workload at its configured size: 32 maps with axes uniform
+    in 64..256 x 64..256 x 64..128, each with its own frame of 50k-300k
+    points and 16 look-ahead states x 20 spheres.  Every map's d2, site and
+    query records against the oracle, for the persistent launch, one launch
+    per pass, and both captured as graphs."""
+    from paper_2407_02363_amd.batch_cycle import BatchCycle
+    bi = inputs.batch_inputs(seed=0, n_maps=32)
+    say(f"[batch cycle 32] {sum(g.n for g in bi.grids)} voxels, "
+        f"{sum(c.shape[0] for c in bi.clouds)} points")
+    bc = BatchCycle(bi)
+    refs = []
+    for i, g in enumerate(bi.grids):
+        occ = np.zeros(g.shape, np.uint8)
+        oracle_lib.insert_points(g, occ, bi.clouds[i], bi.T_map_cam[i])
+        d2, site = oracle_lib.edt(occ)
+        c = bi.centres[i].reshape(-1, 3)
+        r = np.tile(bi.sphere_radii[i], bi.centres[i].shape[0])
+        refs.append((d2, site, oracle_lib.query_spheres(g, d2, site, c, r)))
+
+    def verify(tag):
+        torch.cuda.synchronize()
+        for i, g in enumerate(bi.grids):
+            assert np.array_equal(bc.d2[i].cpu().numpy().reshape(g.shape), refs[i][0]), (tag, i)
+            assert np.array_equal(bc.site[i].cpu().numpy().reshape(g.shape), refs[i][1]), (tag, i)
+            assert np.array_equal(bc.out[i].cpu().numpy().view(np.uint32), refs[i][2]), (tag, i)
+
+    def poison():
+        for t in bc.d2 + bc.site:
+            t.fill_(-7)
+
+    for name, fn in (("batched", bc.run_batched), ("many", bc.run_many)):
+        say(f"[batch cycle 32] {name}")
+        poison()
+        fn()
+        verify(name)
+        assert not edt.edt_batch_status(bc.ws)
+        graph = bc.capture(fn)
+        for rep in range(2):
+            poison()
+            torch.cuda.synchronize()
+            say(f"[batch cycle 32] {name} graph replay {rep}")
+            graph.replay()
+            verify(f"{name} graph {rep}")
+        del graph
+    assert not edt.edt_batch_status(bc.ws)

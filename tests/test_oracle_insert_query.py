@@ -198,7 +198,8 @@ def test_sphere_rule_closed_form():
     apart (k - 1 >= d3/diameter), so the spheres overlap along the whole long
     axis, and each sphere contains the box's cross-section in its own centre
     plane (the face diagonal is the diameter).  It does not contain the whole
-    box, so the paper's "inscription" is read in that weaker sense."""
+    box, so the paper's claim that the spheres enclose the box is read in that
+    weaker sense."""
     for r, l in [(0.04, 0.2), (0.08, 0.4), (0.06, 0.3), (0.03, 0.07)]:
         c, rad = inputs.bounding_spheres_link(r, l)
         d3 = l + 2 * r

@@ -64,3 +64,26 @@ def test_flooding_can_miss_the_nearest_site():
             assert (d2 >= bd).all()
             return
     pytest.fail("no map with a flooding error found")
+
+
+def test_steps_read_the_previous_round_only():
+    """Each flooding round reads only the previous round's sites (double
+    buffering).  On a 4 x 4 slice with sites at (x, y) = (3, 0) and (1, 2):
+    after the k = 2 round, (3, 2) holds (3, 0) (a tie at d2 = 4 with (1, 2),
+    the smaller index wins) while (2, 2), (2, 3) and (3, 3) are still empty.
+    In the k = 1 round, (3, 3) then sees only (3, 2) and takes (3, 0) at
+    d2 = 9, although (1, 2) at d2 = 5 is nearer.  A round that updated in
+    place, in index order, would already have given (2, 2) the site (1, 2)
+    and passed it on to (3, 3).  The expected slice was traced round by round
+    from the definition of a round."""
+    occ = np.zeros((1, 4, 4), np.uint8)
+    occ[0, 0, 3] = 1
+    occ[0, 2, 1] = 1
+    d2, site = oracle.jfa(occ)
+    want = np.array([3, 3, 3, 3,
+                     9, 9, 3, 3,
+                     9, 9, 9, 3,
+                     9, 9, 9, 3], np.int32).reshape(1, 4, 4)
+    assert np.array_equal(site, want)
+    assert site[0, 3, 3] == 3 and d2[0, 3, 3] == 9
+    check_valid(occ, d2, site)
