@@ -240,6 +240,25 @@ int edt_insert_links(const edt_grid_t* grid, uint8_t* occ, const float* link_pts
                      uint64_t link_mask, void* stream);
 
 /*
+ * edt_clear_insert_links_many -- ClearMap followed by UpdateLinks of Alg. 2
+ * (as edt_clear, then edt_insert_links) for a batch of joint states that
+ * share one grid -- the self map at every look-ahead state -- in two
+ * launches for the whole batch.
+ *   occ        HOST array of n_maps (1..EDT_BATCH_MAX) device pointers, read
+ *              during the call: map j, nx*ny*nz bytes.  Maps must not overlap.
+ *   link_poses float32 [n_maps][n_links][12] device: the link-to-map poses of
+ *              state j at link_poses + 12 * n_links * j.
+ *   link_pts, link_off, n_links, link_mask  as for edt_insert_links.
+ *   gates      nullable DEVICE int32 [n_maps]: map j is cleared and filled
+ *              only if gates[j] != 0 when the kernels run (else untouched).
+ * Each map ends exactly as edt_clear + edt_insert_links leave it.
+ */
+int edt_clear_insert_links_many(const edt_grid_t* grid, uint8_t* const* occ, int32_t n_maps,
+                                const float* link_pts, const int32_t* link_off, int32_t n_links,
+                                const float* link_poses, uint64_t link_mask, const int32_t* gates,
+                                void* stream);
+
+/*
  * edt_workspace_bytes -- device workspace edt_compute needs for this grid
  * (0 for this version: the intermediate lives in the site output).
  */
@@ -361,6 +380,24 @@ typedef struct edt_batch_map_t {
 int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuning_t* tuning,
                      void* stream);
 
+/*
+ * edt_compute_many_gated -- edt_compute_many in which the device decides,
+ * map by map, whether a map is transformed: for batches whose members are
+ * chosen by earlier kernels (the look-ahead states whose predicted self
+ * distances cannot be trusted, sdf_mlp_fallback), with no round trip to
+ * the host in between.
+ *   gates   DEVICE int32 [n_maps], or NULL (= edt_compute_many).  Map i is
+ *           transformed only if gates[i] != 0; if it is 0, every work-group
+ *           of map i returns at once and its d2 and site are left exactly as
+ *           they were.  The kernels read gates when they run, so the values
+ *           must be written before the call in stream order and must not
+ *           change until it has finished; a captured graph reads them anew
+ *           on every replay.
+ * Everything else as for edt_compute_many.
+ */
+int edt_compute_many_gated(const edt_batch_map_t* maps, int32_t n_maps, const int32_t* gates,
+                           const edt_tuning_t* tuning, void* stream);
+
 /* Workspace bytes for a batch of n_maps (queue head, error flag, one
  * counter per map). */
 size_t edt_batch_workspace_bytes(int32_t n_maps);
@@ -430,6 +467,21 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
 int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* site,
                       const float* centres, const float* radii, int32_t m,
                       edt_sphere_result_t* out, void* stream);
+
+/*
+ * edt_query_spheres_many -- edt_query_spheres for a batch of maps of one
+ * grid in one launch (the m bounding spheres at every look-ahead state).
+ *   d2, site  HOST arrays of n_maps (1..EDT_BATCH_MAX) device pointers, read
+ *             during the call: the outputs of the transform of map j.
+ *   centres   float32 [n_maps][m][3] device: state j's sphere centres.
+ *   radii     float32 [m] device, shared by every state.
+ *   out       edt_sphere_result_t [n_maps][m] device.
+ * Record (j, k) is exactly what edt_query_spheres gives for map j, centre
+ * k.
+ */
+int edt_query_spheres_many(const edt_grid_t* grid, const int32_t* const* d2,
+                           const int32_t* const* site, int32_t n_maps, const float* centres,
+                           const float* radii, int32_t m, edt_sphere_result_t* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -123,6 +123,23 @@ int sdf_mlp_fallback(const float* y, const float* radii, const float* eps_vox, i
                      float voxel, float margin, int32_t* need, int32_t* count, void* stream);
 
 /*
+ * sdf_mlp_select -- the distances a look-ahead batch ends with: the exact
+ * ones for the states that needed the exact self-map transform, the
+ * predictions for the rest.  For every state b and sphere i:
+ *   out[b][i] = need[b] != 0 ? exact[b * exact_row + i * exact_col] : y[b][i]
+ *   y, out   float32 [batch][12] device, voxels (out may be y).
+ *   need     int32 [batch] device: sdf_mlp_fallback's output.
+ *   exact    float32 device, strided by exact_row / exact_col floats, so the
+ *            dist_vox word of edt_sphere_result_t records can be read in
+ *            place (records [batch][12] of 16 words: exact = &rec->dist_vox,
+ *            exact_row = 192, exact_col = 16).  Rows with need[b] == 0 are
+ *            not read.
+ * A selection, no arithmetic: the copied values keep their bits.
+ */
+int sdf_mlp_select(const float* y, const int32_t* need, const float* exact, int32_t exact_row,
+                   int32_t exact_col, int32_t batch, float* out, void* stream);
+
+/*
  * sdf_mlp_calibrate -- the error bound the fallback rule allows for, from
  * held-out states with exact labels.  For every sphere i:
  *   eps_vox[i] = max(0, max over rows b with target[b][i] < clip_vox of

@@ -75,18 +75,19 @@ struct EdtMap {
     int nx, ny, nz;
     int ntx;         // column tiles per row of this pass
     int begin;       // first tile of this map in the launch
+    const int* gate; // nullable: this map's work-groups do nothing while *gate == 0
 };
 struct EdtMapSet {
     int n;
     int total;       // tiles of all maps
     int ny_max, nz_max;
     bool wide;
-    const int* gate; // nullable: the launch does nothing while *gate == 0
     EdtMap m[EDT_BATCH_MAX];
 };
-// Validates the maps and the tiles and fills the two passes' sets.
+// Validates the maps and the tiles and fills the two passes' sets; gates
+// (nullable, device int [n]) switch maps off from the device.
 int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMapSet& xy,
-                  EdtMapSet& z);
+                  EdtMapSet& z, const int* gates = nullptr);
 int launch_edt_xy_set(const EdtMapSet& s, int tw, int nt, hipStream_t st);
 int launch_edt_z_set(const EdtMapSet& s, int tw, int nt, hipStream_t st);
 

@@ -216,11 +216,11 @@ struct LinkSegs {
     int prefix[MAX_LINKS + 1];   // first thread of segment s
 };
 
-__global__ void k_insert_links(GridArgs g, const float* __restrict__ link_pts, LinkSegs segs,
-                               const float* __restrict__ poses, uint8_t* __restrict__ occ)
+// Link point i of the selected segments, placed by its link's pose.
+__device__ __forceinline__ void insert_link_point(const GridArgs& g, const float* link_pts,
+                                                  const LinkSegs& segs, const float* poses, int i,
+                                                  uint8_t* occ)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= segs.prefix[segs.n]) return;
     int s = 0;
     while (s + 1 < segs.n && segs.prefix[s + 1] <= i) ++s;
     const int64_t p = segs.start[s] + (int64_t)(i - segs.prefix[s]);
@@ -231,18 +231,61 @@ __global__ void k_insert_links(GridArgs g, const float* __restrict__ link_pts, L
     insert_point(g, t, link_pts[3 * p], link_pts[3 * p + 1], link_pts[3 * p + 2], occ, nullptr);
 }
 
+__global__ void k_insert_links(GridArgs g, const float* __restrict__ link_pts, LinkSegs segs,
+                               const float* __restrict__ poses, uint8_t* __restrict__ occ)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= segs.prefix[segs.n]) return;
+    insert_link_point(g, link_pts, segs, poses, i, occ);
+}
+
+// Maps of one grid, batched over blockIdx.y: map j is occ[j] (its link poses
+// at poses + j * pose_stride floats); a map whose gate is 0 is left alone.
+struct MapBytes {
+    uint8_t* occ[EDT_BATCH_MAX];
+};
+
+__device__ __forceinline__ bool map_gated_off(const int* gates, int j)
+{
+    return gates && __builtin_amdgcn_readfirstlane(gates[j]) == 0;
+}
+
+// Zero n bytes of every map: 16-byte stores over each map's aligned body,
+// bytes for its head and tail.
+__global__ void k_clear_many(MapBytes m, int64_t n, const int* __restrict__ gates)
+{
+    const int j = blockIdx.y;
+    if (map_gated_off(gates, j)) return;
+    uint8_t* p = m.occ[j];
+    const int64_t head = min(n, (int64_t)((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15));
+    const int64_t body = (n - head) >> 4;
+    const int64_t tail = n - head - 16 * body;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < body) reinterpret_cast<uint4*>(p + head)[i] = make_uint4(0, 0, 0, 0);
+    if (i < head) p[i] = 0;
+    if (i < tail) p[head + 16 * body + i] = 0;
+}
+
+__global__ void k_insert_links_many(GridArgs g, const float* __restrict__ link_pts, LinkSegs segs,
+                                    const float* __restrict__ poses, int64_t pose_stride, MapBytes m,
+                                    const int* __restrict__ gates)
+{
+    const int j = blockIdx.y;
+    if (map_gated_off(gates, j)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= segs.prefix[segs.n]) return;
+    insert_link_point(g, link_pts, segs, poses + j * pose_stride, i, m.occ[j]);
+}
+
 __device__ __forceinline__ float dist_at(const int32_t* d2, int64_t lin)
 {
     return sqrtf((float)d2[lin]);
 }
 
-__global__ void k_query_spheres(GridArgs g, const int32_t* __restrict__ d2,
-                                const int32_t* __restrict__ site, const float* __restrict__ centres,
-                                const float* __restrict__ radii, int m,
-                                edt_sphere_result_t* __restrict__ out)
+__device__ void query_sphere(const GridArgs& g, const int32_t* __restrict__ d2,
+                             const int32_t* __restrict__ site, const float* __restrict__ centres,
+                             const float* __restrict__ radii, int i, edt_sphere_result_t* __restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
     const float c[3] = {centres[3 * i], centres[3 * i + 1], centres[3 * i + 2]};
     const float r = radii[i];
     const float o[3] = {g.ox, g.oy, g.oz};
@@ -306,6 +349,32 @@ __global__ void k_query_spheres(GridArgs g, const int32_t* __restrict__ d2,
         res.grad[a] = gr;
     }
     out[i] = res;
+}
+
+__global__ void k_query_spheres(GridArgs g, const int32_t* __restrict__ d2,
+                                const int32_t* __restrict__ site, const float* __restrict__ centres,
+                                const float* __restrict__ radii, int m,
+                                edt_sphere_result_t* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    query_sphere(g, d2, site, centres, radii, i, out);
+}
+
+struct MapFields {
+    const int32_t* d2[EDT_BATCH_MAX];
+    const int32_t* site[EDT_BATCH_MAX];
+};
+
+// Sphere k of state j is thread k of row j (blockIdx.y).
+__global__ void k_query_spheres_many(GridArgs g, MapFields f, const float* __restrict__ centres,
+                                     const float* __restrict__ radii, int m,
+                                     edt_sphere_result_t* __restrict__ out)
+{
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    query_sphere(g, f.d2[j], f.site[j], centres + (size_t)3 * m * j, radii, i, out + (size_t)m * j);
 }
 
 GridArgs grid_args(const edt_grid_t* g)
@@ -493,25 +562,27 @@ int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, c
     return check_launch("k_logodds_update");
 }
 
-int edt_insert_links(const edt_grid_t* grid, uint8_t* occ, const float* link_pts,
-                     const int32_t* link_off, int32_t n_links, const float* poses,
-                     uint64_t mask, void* stream)
+}  // extern "C"
+
+namespace {
+// The selected links' point ranges (link_off, n_links, mask as for
+// edt_insert_links), validated; total = their points.
+int link_segments(const char* who, const int32_t* link_off, int32_t n_links, uint64_t mask,
+                  const float* link_pts, LinkSegs& segs, int64_t& total)
 {
-    int rc = check_grid(grid);
-    if (rc) return rc;
-    if (!occ || !link_off || !poses || n_links < 1 || n_links > MAX_LINKS) {
-        set_error("edt_insert_links: bad pointer or link count %d", n_links);
+    if (!link_off || n_links < 1 || n_links > MAX_LINKS) {
+        set_error("%s: link_off is NULL or link count %d outside 1..%d", who, n_links, MAX_LINKS);
         return EDT_ERR_ARG;
     }
     if (link_off[0] != 0) {
-        set_error("edt_insert_links: link_off[0] must be 0");
+        set_error("%s: link_off[0] must be 0", who);
         return EDT_ERR_ARG;
     }
-    LinkSegs segs{};
-    int64_t total = 0;
+    segs = LinkSegs{};
+    total = 0;
     for (int l = 0; l < n_links; ++l) {
         if (link_off[l + 1] < link_off[l]) {
-            set_error("edt_insert_links: link_off not non-decreasing at %d", l);
+            set_error("%s: link_off not non-decreasing at %d", who, l);
             return EDT_ERR_ARG;
         }
         if (!((mask >> l) & 1u)) continue;
@@ -524,19 +595,75 @@ int edt_insert_links(const edt_grid_t* grid, uint8_t* occ, const float* link_pts
         ++segs.n;
     }
     if (total > INT_MAX - 256) {
-        set_error("edt_insert_links: too many link points");
+        set_error("%s: too many link points", who);
         return EDT_ERR_ARG;
     }
     segs.prefix[segs.n] = (int)total;
-    if (total == 0) return EDT_OK;
-    if (!link_pts) {
-        set_error("edt_insert_links: link_pts is NULL");
+    if (total > 0 && !link_pts) {
+        set_error("%s: link_pts is NULL", who);
         return EDT_ERR_ARG;
     }
+    return EDT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int edt_insert_links(const edt_grid_t* grid, uint8_t* occ, const float* link_pts,
+                     const int32_t* link_off, int32_t n_links, const float* poses,
+                     uint64_t mask, void* stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!occ || !poses) {
+        set_error("edt_insert_links: occ or poses is NULL");
+        return EDT_ERR_ARG;
+    }
+    LinkSegs segs;
+    int64_t total;
+    if ((rc = link_segments("edt_insert_links", link_off, n_links, mask, link_pts, segs, total))) return rc;
+    if (total == 0) return EDT_OK;
     const int blocks = (int)((total + 255) / 256);
     hipLaunchKernelGGL(k_insert_links, dim3(blocks), dim3(256), 0, as_stream(stream),
                        grid_args(grid), link_pts, segs, poses, occ);
     return check_launch("k_insert_links");
+}
+
+int edt_clear_insert_links_many(const edt_grid_t* grid, uint8_t* const* occ, int32_t n_maps,
+                                const float* link_pts, const int32_t* link_off, int32_t n_links,
+                                const float* link_poses, uint64_t link_mask, const int32_t* gates,
+                                void* stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!occ || !link_poses || n_maps < 1 || n_maps > EDT_BATCH_MAX) {
+        set_error("edt_clear_insert_links_many: NULL occ or link_poses, or %d maps outside 1..%d",
+                  n_maps, EDT_BATCH_MAX);
+        return EDT_ERR_ARG;
+    }
+    LinkSegs segs;
+    int64_t total;
+    if ((rc = link_segments("edt_clear_insert_links_many", link_off, n_links, link_mask, link_pts, segs,
+                            total)))
+        return rc;
+    MapBytes m;
+    for (int j = 0; j < n_maps; ++j) {
+        if (!occ[j]) {
+            set_error("edt_clear_insert_links_many: occ[%d] is NULL", j);
+            return EDT_ERR_ARG;
+        }
+        m.occ[j] = occ[j];
+    }
+    const hipStream_t st = as_stream(stream);
+    const int64_t n = grid_voxels(grid);
+    const int64_t threads = std::max<int64_t>(n >> 4, 16);
+    hipLaunchKernelGGL(k_clear_many, dim3((unsigned)((threads + 255) / 256), n_maps), dim3(256), 0, st, m,
+                       n, gates);
+    if ((rc = check_launch("k_clear_many"))) return rc;
+    if (total == 0) return EDT_OK;
+    hipLaunchKernelGGL(k_insert_links_many, dim3((unsigned)((total + 255) / 256), n_maps), dim3(256), 0,
+                       st, grid_args(grid), link_pts, segs, link_poses, (int64_t)12 * n_links, m, gates);
+    return check_launch("k_insert_links_many");
 }
 
 size_t edt_workspace_bytes(const edt_grid_t* grid)
@@ -587,8 +714,8 @@ int edt_compute(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_t
     return edt_compute_stage(grid, occ, d2, site, EDT_STAGE_ALL, nullptr, stream);
 }
 
-int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuning_t* tuning,
-                     void* stream)
+int edt_compute_many_gated(const edt_batch_map_t* maps, int32_t n_maps, const int32_t* gates,
+                           const edt_tuning_t* tuning, void* stream)
 {
     if (!maps || n_maps < 1 || n_maps > EDT_BATCH_MAX) {
         set_error("edt_compute_many: need 1..%d maps, got %d", EDT_BATCH_MAX, n_maps);
@@ -607,13 +734,19 @@ int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuni
         if (check_grid(&big)) return check_grid(&big);
         t = current_tuning(&big);
     }
-    static thread_local EdtMapSet sxy, sz;   // ~2.3 KiB each: kept off the stack
-    int rc = make_map_sets(maps, n_maps, t, sxy, sz);
+    static thread_local EdtMapSet sxy, sz;   // ~2.7 KiB each: kept off the stack
+    int rc = make_map_sets(maps, n_maps, t, sxy, sz, gates);
     if (rc) return rc;
     const hipStream_t st = as_stream(stream);
     rc = launch_edt_xy_set(sxy, t.xy_tw, t.xy_nt, st);
     if (!rc) rc = launch_edt_z_set(sz, t.z_tw, t.z_nt, st);
     return rc;
+}
+
+int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuning_t* tuning,
+                     void* stream)
+{
+    return edt_compute_many_gated(maps, n_maps, nullptr, tuning, stream);
 }
 
 size_t edt_cache_workspace_bytes(const edt_grid_t* grid)
@@ -670,6 +803,33 @@ int edt_compute_cached(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, 
     if (rc) return rc;
     hipLaunchKernelGGL(k_cache_end, dim3(1), dim3(1), 0, st, flags);
     return check_launch("k_cache_end");
+}
+
+int edt_query_spheres_many(const edt_grid_t* grid, const int32_t* const* d2,
+                           const int32_t* const* site, int32_t n_maps, const float* centres,
+                           const float* radii, int32_t m, edt_sphere_result_t* out, void* stream)
+{
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!d2 || !site || n_maps < 1 || n_maps > EDT_BATCH_MAX || m < 0 ||
+        (m > 0 && (!centres || !radii || !out))) {
+        set_error("edt_query_spheres_many: bad pointer, %d maps outside 1..%d or negative count", n_maps,
+                  EDT_BATCH_MAX);
+        return EDT_ERR_ARG;
+    }
+    MapFields f;
+    for (int j = 0; j < n_maps; ++j) {
+        if (!d2[j] || !site[j]) {
+            set_error("edt_query_spheres_many: d2[%d] or site[%d] is NULL", j, j);
+            return EDT_ERR_ARG;
+        }
+        f.d2[j] = d2[j];
+        f.site[j] = site[j];
+    }
+    if (m == 0) return EDT_OK;
+    hipLaunchKernelGGL(k_query_spheres_many, dim3((m + 63) / 64, n_maps), dim3(64), 0, as_stream(stream),
+                       grid_args(grid), f, centres, radii, m, out);
+    return check_launch("k_query_spheres_many");
 }
 
 int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* site,

@@ -21,16 +21,22 @@ __device__ __forceinline__ int map_of(const EdtMapSet& s, int T)
     return __builtin_amdgcn_readfirstlane(m);
 }
 
+// True while the map's gate (if any) holds 0: its work-groups return at once.
+__device__ __forceinline__ bool gated_off(const EdtMap& d)
+{
+    return d.gate && __builtin_amdgcn_readfirstlane(*d.gate) == 0;
+}
+
 template <int TW, bool WIDE, int NTX>
 __global__ __launch_bounds__(NTX) void k_edt_xy(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
-    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     // the tiles of a slice read the same occupancy bytes: chunks of 16 tiles
     // (one or two slices) share an XCD's L2, and the slices, whose work is
     // very uneven, rotate over the XCDs
     const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
     const EdtMap& d = s.m[map_of(s, T)];
+    if (gated_off(d)) return;
     edt_xy_tile<TW, WIDE, NTX>(d.occ, reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny, d.nz, d.ntx,
                                T - d.begin, lds);
 }
@@ -40,10 +46,10 @@ __global__ __launch_bounds__(NTX) void k_edt_xy(EdtMapSet s)
 // s.m[i].begin is the map's first wave.
 __global__ __launch_bounds__(256) void k_row_records(EdtMapSet s)
 {
-    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     const int wv = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
     if (wv >= s.total) return;
     const EdtMap& d = s.m[map_of(s, wv)];
+    if (gated_off(d)) return;
     const int per = record_rows_per_wave(d.occ, d.nx);
     const int row0 = (wv - d.begin) * per;
     const int nrows = min(per, d.ny * d.nz - row0);
@@ -58,10 +64,10 @@ template <int TW, bool WIDE, int NTX>
 __global__ __launch_bounds__(NTX) void k_edt_xy_rows(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
-    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     // as in k_edt_xy: chunks of 16 tiles per XCD, rotating over the XCDs
     const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
     const EdtMap& d = s.m[map_of(s, T)];
+    if (gated_off(d)) return;
     edt_xy_tile_rows<TW, WIDE, NTX>(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site),
                                     d.nx, d.ny, d.ntx, T - d.begin, lds);
 }
@@ -70,30 +76,30 @@ template <int TW, bool WIDE, int NTZ>
 __global__ __launch_bounds__(NTZ) void k_edt_z(EdtMapSet s)
 {
     extern __shared__ uint32_t lds[];
-    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     // tiles narrower than 64 columns share cache lines with their neighbours:
     // the tiles of 64 columns of a row stay on one XCD, and rows (whose work
     // is very uneven) rotate over all eight
     const int T = TW >= 64 ? (int)blockIdx.x : xcd_chunk_remap(blockIdx.x, s.total, 64 / TW);
     const EdtMap& d = s.m[map_of(s, T)];
+    if (gated_off(d)) return;
     edt_z_tile<TW, WIDE, NTZ>(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, lds);
 }
 
 // Lean tiles (edt_lean.h): 64 columns, one wave per band.
 __global__ __launch_bounds__(256) void k_edt_z_lean(EdtMapSet s)
 {
-    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     const int T = (int)blockIdx.x;
     const EdtMap& d = s.m[map_of(s, T)];
+    if (gated_off(d)) return;
     lean::z_tile(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin);
 }
 
 __global__ __launch_bounds__(512) void k_edt_xy_lean(EdtMapSet s)
 {
-    if (s.gate && __builtin_amdgcn_readfirstlane(*s.gate) == 0) return;
     // as in k_edt_xy: chunks of 16 tiles per XCD, rotating over the XCDs
     const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
     const EdtMap& d = s.m[map_of(s, T)];
+    if (gated_off(d)) return;
     lean::xy_tile(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny,
                   d.ntx, T - d.begin);
 }
@@ -210,13 +216,13 @@ int launch_z_tw(const EdtMapSet& s, hipStream_t st)
 
 // The tiles of every map of the set, ntx column tiles of width tw per row
 // of the pass (rows: z slices for xy, y rows for z).
-void fill_set(const edt_batch_map_t* maps, int n, int tw, bool z_pass, EdtMapSet& s)
+void fill_set(const edt_batch_map_t* maps, int n, int tw, bool z_pass, EdtMapSet& s,
+              const int* gates)
 {
     s.n = n;
     s.total = 0;
     s.ny_max = s.nz_max = 0;
     s.wide = false;
-    s.gate = nullptr;
     for (int i = 0; i < n; ++i) {
         const edt_grid_t& g = maps[i].grid;
         EdtMap& d = s.m[i];
@@ -228,6 +234,7 @@ void fill_set(const edt_batch_map_t* maps, int n, int tw, bool z_pass, EdtMapSet
         d.nz = g.nz;
         d.ntx = (g.nx + tw - 1) / tw;
         d.begin = s.total;
+        d.gate = gates ? gates + i : nullptr;
         s.total += (z_pass ? g.ny : g.nz) * d.ntx;
         s.ny_max = std::max(s.ny_max, g.ny);
         s.nz_max = std::max(s.nz_max, g.nz);
@@ -281,7 +288,7 @@ EdtTuning default_tuning(const edt_grid_t* g)
 }
 
 int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMapSet& xy,
-                  EdtMapSet& z)
+                  EdtMapSet& z, const int* gates)
 {
     if (!maps || n < 1 || n > EDT_BATCH_MAX) {
         set_error("need 1..%d maps, got %d", EDT_BATCH_MAX, n);
@@ -306,8 +313,8 @@ int make_map_sets(const edt_batch_map_t* maps, int n, const EdtTuning& t, EdtMap
                   t.z_tw, t.z_nt, big.nx, big.ny, big.nz);
         return EDT_ERR_UNSUPPORTED;
     }
-    fill_set(maps, n, t.xy_tw, false, xy);
-    fill_set(maps, n, t.z_tw, true, z);
+    fill_set(maps, n, t.xy_tw, false, xy, gates);
+    fill_set(maps, n, t.z_tw, true, z, gates);
     return EDT_OK;
 }
 
@@ -387,8 +394,7 @@ int launch_edt_xy(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, uint32_t
 {
     const edt_batch_map_t m = one_map(g, occ, d2, reinterpret_cast<int32_t*>(xy));
     EdtMapSet s;
-    fill_set(&m, 1, tw, false, s);
-    s.gate = gate;
+    fill_set(&m, 1, tw, false, s, gate);
     return launch_edt_xy_set(s, tw, nt, st);
 }
 
@@ -397,8 +403,7 @@ int launch_edt_z(const edt_grid_t* g, int32_t* d2, int32_t* site, int tw, int nt
 {
     const edt_batch_map_t m = one_map(g, nullptr, d2, site);
     EdtMapSet s;
-    fill_set(&m, 1, tw, true, s);
-    s.gate = gate;
+    fill_set(&m, 1, tw, true, s, gate);
     return launch_edt_z_set(s, tw, nt, st);
 }
 

@@ -399,6 +399,17 @@ __global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ y,
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(count, (int)__popcll(bal));
 }
 
+// out[b][i] = need[b] ? exact[b * erow + i * ecol] : y[b][i]
+__global__ void k_select(const float* __restrict__ y, const int* __restrict__ need,
+                         const float* __restrict__ exact, int erow, int ecol, int batch,
+                         float* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= batch * SDF_MLP_OUT) return;
+    const int b = k / SDF_MLP_OUT, i = k % SDF_MLP_OUT;
+    out[k] = need[b] ? exact[(size_t)b * erow + (size_t)i * ecol] : y[k];
+}
+
 __global__ void k_zero_int(int* p) { *p = 0; }
 
 __global__ void k_zero_f32(float* p, int n)
@@ -629,6 +640,19 @@ int sdf_mlp_fallback(const float* y, const float* radii, const float* eps_vox, i
     hipLaunchKernelGGL(k_fallback, dim3((batch + 255) / 256), dim3(256), 0, st, y, radii, eps_vox,
                        (int)batch, voxel, margin, need, count);
     return check_launch("k_fallback");
+}
+
+int sdf_mlp_select(const float* y, const int32_t* need, const float* exact, int32_t exact_row,
+                   int32_t exact_col, int32_t batch, float* out, void* stream)
+{
+    if (!y || !need || !exact || !out || batch < 1 || exact_row < 0 || exact_col < 0) {
+        set_error("sdf_mlp_select: NULL pointer, batch < 1 or negative stride");
+        return EDT_ERR_ARG;
+    }
+    const int n = batch * SDF_MLP_OUT;
+    hipLaunchKernelGGL(k_select, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), y, need, exact,
+                       (int)exact_row, (int)exact_col, (int)batch, out);
+    return check_launch("k_select");
 }
 
 int sdf_mlp_calibrate(const float* pred, const float* target, int32_t batch, float clip_vox,

@@ -70,7 +70,8 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_update_logodds", "edt_outlier_workspace_bytes", "edt_outlier_filter",
             "edt_cache_workspace_bytes", "edt_cache_reset", "edt_compute_cached",
             "edt_jfa_workspace_bytes", "edt_jfa",
-            "edt_autotune_batched", "edt_compute_batched_noalloc"]
+            "edt_autotune_batched", "edt_compute_batched_noalloc", "edt_compute_many_gated",
+            "edt_clear_insert_links_many", "edt_query_spheres_many"]
 
 BATCH_MAX = 48
 
@@ -98,6 +99,8 @@ def lib():
         "edt_workspace_bytes": ([G], ctypes.c_size_t),
         "edt_compute": ([G, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_query_spheres": ([G, P, P, P, P, i32, P, P], ctypes.c_int),
+        "edt_clear_insert_links_many": ([G, P, i32, P, P, i32, P, u64, P, P], ctypes.c_int),
+        "edt_query_spheres_many": ([G, P, P, i32, P, P, i32, P, P], ctypes.c_int),
         "edt_compute_stage": ([G, P, P, P, ctypes.c_int, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_default_tuning": ([G, ctypes.POINTER(Tuning)], ctypes.c_int),
         "edt_compute_tuned": ([G, P, P, P, ctypes.POINTER(Tuning), P], ctypes.c_int),
@@ -106,6 +109,7 @@ def lib():
         "edt_batch_workspace_bytes": ([i32], ctypes.c_size_t),
         "edt_compute_batched": ([P, i32, P, ctypes.c_size_t, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_compute_many": ([P, i32, ctypes.POINTER(Tuning), P], ctypes.c_int),
+        "edt_compute_many_gated": ([P, i32, P, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_compute_batched_noalloc": ([P, i32, ctypes.POINTER(Tuning), P, P], ctypes.c_int),
         "edt_logodds_workspace_bytes": ([G], ctypes.c_size_t),
         "edt_logodds_reset": ([G, P, P, ctypes.c_size_t, P], ctypes.c_int),
@@ -200,6 +204,49 @@ def edt_insert_links(grid, occ, link_pts, link_off, link_poses, link_mask: int, 
                                   _dev(link_poses, torch.float32, "link_poses", 12 * n_links),
                                   ctypes.c_uint64(link_mask), _stream(stream)),
            "edt_insert_links")
+
+
+def ptr_array(tensors, dtype, name, numel):
+    """Host array of the device pointers of several tensors (for the
+    entry points that take one buffer per map); the caller keeps the tensors
+    alive."""
+    arr = (ctypes.c_void_p * len(tensors))()
+    for j, t in enumerate(tensors):
+        arr[j] = _dev(t, dtype, f"{name}[{j}]", numel).value
+    return arr
+
+
+def edt_clear_insert_links_many(grid, occs, link_pts, link_off, link_poses, link_mask: int,
+                                gates=None, stream=None):
+    """Clear every map of occs (uint8 device tensors of one grid), then insert
+    the links of link_mask placed by link_poses[j] (float32 device
+    [n_maps, n_links, 12]) into map j; gates: None or int32 device [n_maps]."""
+    g = make_grid(grid)
+    off = np.ascontiguousarray(np.asarray(link_off, dtype=np.int32))
+    n_links = off.size - 1
+    k = len(occs)
+    occ_arr = ptr_array(occs, torch.uint8, "occ", _n(g))
+    _check(lib().edt_clear_insert_links_many(
+        ctypes.byref(g), ctypes.cast(occ_arr, ctypes.c_void_p), k,
+        _dev(link_pts, torch.float32, "link_pts", 3 * int(off[-1])),
+        off.ctypes.data_as(ctypes.c_void_p), n_links,
+        _dev(link_poses, torch.float32, "link_poses", 12 * n_links * k), ctypes.c_uint64(link_mask),
+        _dev(gates, torch.int32, "gates", k), _stream(stream)), "edt_clear_insert_links_many")
+
+
+def edt_query_spheres_many(grid, d2s, sites, centres, radii, out, stream=None):
+    """Sphere queries of several maps of one grid: centres float32 device
+    [n_maps, m, 3], radii [m], out int32 device [n_maps, m, 16]."""
+    g = make_grid(grid)
+    m = radii.numel()
+    k = len(d2s)
+    d2_arr = ptr_array(d2s, torch.int32, "d2", _n(g))
+    site_arr = ptr_array(sites, torch.int32, "site", _n(g))
+    _check(lib().edt_query_spheres_many(
+        ctypes.byref(g), ctypes.cast(d2_arr, ctypes.c_void_p), ctypes.cast(site_arr, ctypes.c_void_p), k,
+        _dev(centres, torch.float32, "centres", 3 * m * k), _dev(radii, torch.float32, "radii", m), m,
+        _dev(out, torch.int32, "out", SPHERE_RESULT_WORDS * m * k), _stream(stream)),
+        "edt_query_spheres_many")
 
 
 def edt_workspace_bytes(grid) -> int:
@@ -310,6 +357,15 @@ def edt_compute_many(maps, tuning=None, stream=None):
     _check(lib().edt_compute_many(ctypes.cast(maps, ctypes.c_void_p), len(maps), _tuning(tuning),
                                   _stream(stream)),
            "edt_compute_many")
+
+
+def edt_compute_many_gated(maps, gates, tuning=None, stream=None):
+    """edt_compute_many where map i is transformed only if the int32 device
+    value gates[i] is nonzero when the kernels run (else left untouched)."""
+    _check(lib().edt_compute_many_gated(ctypes.cast(maps, ctypes.c_void_p), len(maps),
+                                        _dev(gates, torch.int32, "gates", len(maps)),
+                                        _tuning(tuning), _stream(stream)),
+           "edt_compute_many_gated")
 
 
 def edt_compute_batched(maps, ws, tuning=None, stream=None):

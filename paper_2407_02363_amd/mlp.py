@@ -21,7 +21,7 @@ LAYOUT = [(W1, B1, N_HIDDEN, IN_PAD), (W2, B2, N_HIDDEN, N_HIDDEN), (W3, B3, N_H
 REAL = [(N_HIDDEN, N_IN), (N_HIDDEN, N_HIDDEN), (N_HIDDEN, N_HIDDEN), (N_OUT, N_HIDDEN)]
 
 EXPORTED = ["sdf_mlp_workspace_bytes", "sdf_mlp_pack", "sdf_mlp_forward", "sdf_mlp_backward",
-            "sdf_mlp_adam", "sdf_mlp_fallback", "sdf_mlp_calibrate"]
+            "sdf_mlp_adam", "sdf_mlp_fallback", "sdf_mlp_calibrate", "sdf_mlp_select"]
 _sig_done = False
 
 
@@ -38,6 +38,7 @@ def lib():
             "sdf_mlp_adam": ([P, P, P, P, P, i32, f, f, f, f, P], ctypes.c_int),
             "sdf_mlp_fallback": ([P, P, P, i32, f, f, P, P, P], ctypes.c_int),
             "sdf_mlp_calibrate": ([P, P, i32, f, P, P], ctypes.c_int),
+            "sdf_mlp_select": ([P, P, P, i32, i32, i32, P, P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -118,6 +119,20 @@ def sdf_mlp_fallback(y, radii, eps_vox, voxel, margin, need, count, stream=None)
                                   float(margin), _dev(need, torch.int32, "need", b),
                                   _dev(count, torch.int32, "count", 1), _stream(stream)),
            "sdf_mlp_fallback")
+
+
+def sdf_mlp_select(y, need, exact, out, stream=None):
+    """out[b] = exact[b] where need[b] != 0, else y[b]; exact is a float32
+    device view [batch, 12] with any strides (e.g. the dist_vox words of
+    sphere query records), y and out contiguous [batch, 12]."""
+    b = y.shape[0]
+    if exact.dtype != torch.float32 or not exact.is_cuda or tuple(exact.shape) != (b, N_OUT):
+        raise ValueError("exact must be a float32 device view of shape [batch, 12]")
+    _check(lib().sdf_mlp_select(_dev(y, torch.float32, "y", N_OUT * b),
+                                _dev(need, torch.int32, "need", b),
+                                ctypes.c_void_p(exact.data_ptr()), exact.stride(0), exact.stride(1), b,
+                                _dev(out, torch.float32, "out", N_OUT * b), _stream(stream)),
+           "sdf_mlp_select")
 
 
 def sdf_mlp_calibrate(pred, target, clip_vox, eps_vox, stream=None):

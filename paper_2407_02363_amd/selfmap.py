@@ -1,12 +1,12 @@
 """Exact self-map distances at the arm's sphere centres for many joint states.
 
-For each state (Alg. 2 lines for the self map): ClearMap, insert the voxel
+For each state (Alg. 2 steps for the self map): ClearMap, insert the voxel
 models of the obstacle links O_L placed by the state's forward kinematics,
 compute the exact EDT, and read sqrt(d2) at every sphere centre
 (ExtractClosestObstaclePose).  States go in chunks of up to EDT_BATCH_MAX
-maps: one edt_compute_many per chunk (one launch per pass over every map of
-the chunk; edt_mode="batched" uses the persistent batched launch), and the
-whole chunk is
+maps, each step one launch (or one per pass) for the whole chunk:
+edt_clear_insert_links_many, edt_compute_many (edt_mode="batched" uses the
+persistent batched launch), edt_query_spheres_many; and the whole chunk is
 replayed from a HIP graph whose pose and centre buffers are refilled before
 every replay.  Graphs exist for chunk sizes 1, 2, 4, ... and the full
 chunk, so a partial chunk (the states the surrogate could not clear, for
@@ -45,6 +45,10 @@ class SelfMapLabeler:
         self.out = torch.empty((c, len(setup.sphere_radii), edt.SPHERE_RESULT_WORDS),
                                dtype=torch.int32, device=d)
         self.link_pts = torch.from_numpy(setup.link_pts).to(d)
+        # per-slot switches of the gated transform (run_chunk(gated=True)):
+        # slot i is transformed only while gate[i] != 0, a value kernels
+        # earlier in the stream may write
+        self.gate = torch.ones(c, dtype=torch.int32, device=d)
         sizes = [1 << k for k in range(7) if (1 << k) < c] + [c]
         self.maps = {k: edt.batch_maps([g] * k, self.occ[:k], self.d2[:k], self.site[:k])
                      for k in sizes}
@@ -65,22 +69,28 @@ class SelfMapLabeler:
         """Smallest chunk size with a batch plan that holds k states."""
         return min(s for s in self.maps if s >= k)
 
-    def run_chunk(self, k=None, stream=None):
+    def run_chunk(self, k=None, stream=None, gated=False):
         """Clear, insert, transform and query the first k maps (k must be a
-        planned size; None = the full chunk)."""
+        planned size; None = the full chunk).  gated: the transform skips
+        every slot whose gate is 0 (its distances are then stale)."""
         g = self.s.grid
         k = self.chunk if k is None else k
-        for i in range(k):
-            edt.edt_clear(g, self.occ[i], stream)
-            edt.edt_insert_links(g, self.occ[i], self.link_pts, self.s.link_off, self.poses[i],
-                                 self.s.mask, stream)
-        if self.edt_mode == "many":
+        gates = self.gate[:k] if gated else None
+        edt.edt_clear_insert_links_many(g, self.occ[:k], self.link_pts, self.s.link_off, self.poses[:k],
+                                        self.s.mask, gates, stream)
+        if gated:
+            edt.edt_compute_many_gated(self.maps[k], self.gate[:k], stream=stream)
+        elif self.edt_mode == "many":
             edt.edt_compute_many(self.maps[k], stream=stream)
         else:
             edt.edt_compute_batched(self.maps[k], self.ws, stream=stream)
-        for i in range(k):
-            edt.edt_query_spheres(g, self.d2[i], self.site[i], self.centres[i], self.radii,
-                                  self.out[i], stream)
+        edt.edt_query_spheres_many(g, self.d2[:k], self.site[:k], self.centres[:k], self.radii,
+                                   self.out[:k], stream)
+
+    def exact_view(self, k):
+        """dist_vox of the last run's first k slots: float32 [k, m] view of
+        the query records (strided, on the device)."""
+        return self.out[:k, :, 6].view(torch.float32)
 
     def stage(self, qs: np.ndarray):
         """Host forward kinematics of many states -> device (poses, centres)."""

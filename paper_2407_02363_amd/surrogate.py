@@ -118,3 +118,62 @@ class Surrogate:
             self.eps.copy_(torch.from_numpy(np.asarray(st["eps"], np.float32)))
         self.clip_vox = float(st.get("clip_vox", self.clip_vox))
         mlp.sdf_mlp_pack(self.master, self.w16)
+
+
+class AssistedLookahead:
+    """One look-ahead batch of S joint states with no host round trip: the
+    surrogate predicts every state's sphere distances, sdf_mlp_fallback marks
+    the states it cannot clear, the labeler's gated transform runs the exact
+    self-map EDT for those states only (the others' work-groups return at
+    once), and sdf_mlp_select keeps the exact distances of the marked states
+    and the predictions of the rest.  The whole batch is one HIP graph.
+
+    labeler: a SelfMapLabeler whose full chunk is S states; its gate buffer
+    receives the fallback flags.  The distances are those of the states last
+    staged with run(); the result buffer is overwritten by every run."""
+
+    def __init__(self, sur: Surrogate, labeler, radii, voxel: float, margin: float,
+                 use_graph: bool = True):
+        self.sur = sur
+        self.lab = labeler
+        S = labeler.chunk
+        self.S = S
+        d = sur.dev
+        self.radii = radii
+        self.voxel = float(voxel)
+        self.margin = float(margin)
+        self.q = torch.zeros((S, mlp.JOINTS), dtype=torch.float32, device=d)
+        self.y = torch.empty((S, mlp.N_OUT), dtype=torch.float32, device=d)
+        self.out = torch.empty((S, mlp.N_OUT), dtype=torch.float32, device=d)
+        self.count = torch.zeros(1, dtype=torch.int32, device=d)
+        self.ws = mlp.new_workspace(S, d)
+        self.need = labeler.gate[:S]
+        self.graph = None
+        if use_graph:
+            self._body()
+            torch.cuda.synchronize(d)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, capture_error_mode="thread_local"):
+                self._body()
+            torch.cuda.synchronize(d)
+            self.graph = g
+
+    def _body(self):
+        s = self.sur
+        mlp.sdf_mlp_forward(s.w16, s.master, self.q, self.y, self.ws)
+        mlp.sdf_mlp_fallback(self.y, self.radii, s.eps, self.voxel, self.margin, self.need, self.count)
+        self.lab.run_chunk(self.S, gated=True)
+        mlp.sdf_mlp_select(self.y, self.need, self.lab.exact_view(self.S), self.out)
+
+    def run(self, q, poses, centres):
+        """q float32 [S, 7], poses / centres as SelfMapLabeler.stage gives
+        them (device).  Returns the [S, 12] distances (voxels, device); need
+        (int32 [S]) and count hold which states took the exact path."""
+        self.q.copy_(q)
+        self.lab.poses[:self.S].copy_(poses)
+        self.lab.centres[:self.S].copy_(centres)
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._body()
+        return self.out

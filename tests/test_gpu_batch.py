@@ -260,3 +260,82 @@ def test_batch_cycle_configured_size(oracle_lib):
             verify(f"{name} graph {rep}")
         del graph
     assert not edt.edt_batch_status(bc.ws)
+
+
+def gated_case(case):
+    """Maps that take each path of the two passes: lean xy + lean z, plain xy,
+    row records + xy from records, the 64-bit (wide) envelope test, and
+    explicit tiles."""
+    tuning = None
+    if case == "lean":
+        shapes = [(128, 128, 128), (100, 200, 64), (64, 256, 96), (128, 128, 128), (77, 64, 64)]
+        occs = [inputs.random_grid(sh, 0.002 * (i + 1), 900 + i) for i, sh in enumerate(shapes)]
+        grids = [inputs.Grid(sh[2], sh[1], sh[0]) for sh in shapes]
+    elif case == "rows":
+        shapes = [(16, 300, 256), (8, 260, 300), (24, 280, 260)]
+        occs = [inputs.random_grid(sh, 0.001 * (i + 1), 920 + i) for i, sh in enumerate(shapes)]
+        grids = [inputs.Grid(sh[2], sh[1], sh[0]) for sh in shapes]
+    else:
+        occs, grids = mixed_batch(4)
+        if case == "wide":
+            occs, grids = occs[:5], grids[:5]
+            occs.append(inputs.random_grid((6, 9, 700), 0.01, 78))
+            grids.append(inputs.Grid(700, 9, 6))
+        elif case == "tiles":
+            tuning = (32, 32, 128)
+    return occs, grids, tuning
+
+
+@pytest.mark.parametrize("case", ["lean", "rows", "mixed", "wide", "tiles"])
+def test_many_gated(oracle_lib, case):
+    """edt_compute_many_gated: a map whose device gate is 0 keeps its d2 and
+    site bit for bit, every other map matches the oracle; flipping the gates
+    in place transforms the rest; a captured graph reads the gates anew on
+    every replay."""
+    occs, grids, tuning = gated_case(case)
+    d = dev()
+    n = len(occs)
+    say(f"[many gated] {case}: {n} maps, tiles {tuning}")
+    refs = [oracle_lib.edt(o) for o in occs]
+    o = [torch.from_numpy(np.ascontiguousarray(x).ravel()).to(d) for x in occs]
+    d2 = [torch.empty(x.size, dtype=torch.int32, device=d) for x in occs]
+    st = [torch.empty(x.size, dtype=torch.int32, device=d) for x in occs]
+    maps = edt.batch_maps(grids, o, d2, st)
+    gates = torch.from_numpy((np.arange(n) % 2).astype(np.int32)).to(d)
+
+    def poison():
+        for i in range(n):
+            d2[i].fill_(-7 - i)
+            st[i].fill_(-100 - i)
+
+    def verify(on, tag):
+        torch.cuda.synchronize()
+        for i, x in enumerate(occs):
+            a = d2[i].cpu().numpy().reshape(x.shape)
+            b = st[i].cpu().numpy().reshape(x.shape)
+            if on[i]:
+                assert np.array_equal(a, refs[i][0]) and np.array_equal(b, refs[i][1]), (tag, i)
+            else:
+                assert (a == -7 - i).all() and (b == -100 - i).all(), (tag, i, "touched")
+
+    poison()
+    edt.edt_compute_many_gated(maps, gates, tuning)
+    on = [bool(i % 2) for i in range(n)]
+    verify(on, "first")
+    gates.copy_(1 - gates)
+    edt.edt_compute_many_gated(maps, gates, tuning)
+    verify([True] * n, "flipped")
+    if case != "lean":
+        return
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, capture_error_mode="thread_local"):
+        edt.edt_compute_many_gated(maps, gates, tuning)
+    torch.cuda.synchronize()
+    for rep, pattern in enumerate(([1, 0, 0, 1, 1], [0, 1, 1, 0, 0], [0, 0, 0, 0, 0], [1, 1, 1, 1, 1])):
+        poison()
+        gates.copy_(torch.tensor(pattern, dtype=torch.int32))
+        torch.cuda.synchronize()
+        say(f"[many gated] graph replay {rep} gates {pattern}")
+        graph.replay()
+        verify([bool(p) for p in pattern], f"graph {rep}")

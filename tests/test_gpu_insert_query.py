@@ -130,3 +130,70 @@ def test_query_empty_and_thin_maps(oracle_lib):
             say(f"[query] thin {shape} occupied={int(occ.sum())}")
             got = run_query(g, d2, site, C, rad)
             assert np.array_equal(got, oracle_lib.query_spheres(g, d2, site, C, rad))
+
+
+def test_clear_insert_links_many(oracle_lib):
+    """One clear launch and one insert launch for a batch of joint states:
+    every map whose gate is set equals the oracle's ClearMap + UpdateLinks for
+    its own state (its old bytes gone), every map whose gate is 0 keeps its
+    bytes; without gates every map is rebuilt.  Maps at odd byte offsets
+    exercise the clear's unaligned head and tail."""
+    st = inputs.self_map_setup()
+    g = st.grid
+    S = 7
+    qs = inputs.random_joint_states(S, 41)
+    poses = np.stack([st.robot.poses12(q) for q in qs]).astype(np.float32)
+    refs = []
+    for q in qs:
+        ref = np.zeros(g.shape, np.uint8)
+        oracle_lib.insert_links(g, ref, st.link_pts, st.link_off, st.robot.poses12(q), st.mask)
+        refs.append(ref)
+    buf = torch.empty(S * (g.n + 3) + 16, dtype=torch.uint8, device=dev())
+    occs = [buf[1 + j * (g.n + 3):1 + j * (g.n + 3) + g.n] for j in range(S)]
+    gates = torch.tensor([1, 0, 1, 1, 0, 0, 1], dtype=torch.int32, device=dev())
+    pts = to_dev(st.link_pts)
+    pd = to_dev(poses)
+    for tag, gt in (("gated", gates), ("all", None)):
+        buf.fill_(0xAB)
+        say(f"[links many] {tag}")
+        edt.edt_clear_insert_links_many(g, occs, pts, st.link_off, pd, st.mask, gt)
+        torch.cuda.synchronize()
+        on = gates.cpu().numpy() if gt is not None else np.ones(S, np.int32)
+        host = buf.cpu().numpy()
+        for j in range(S):
+            got = occs[j].cpu().numpy().reshape(g.shape)
+            if on[j]:
+                assert np.array_equal(got, refs[j]), (tag, j)
+            else:
+                assert (got == 0xAB).all(), (tag, j)
+        # the bytes between and around the maps are never written
+        gaps = np.concatenate([host[:1]] + [host[1 + j * (g.n + 3) + g.n:1 + (j + 1) * (g.n + 3)]
+                                            for j in range(S)])
+        assert (gaps == 0xAB).all(), tag
+
+
+def test_query_spheres_many(oracle_lib):
+    """One launch for the sphere queries of several maps of one grid: record
+    (j, k) equals the oracle's query of map j at centre k, inside, outside and
+    on the border of the map, and on an empty map."""
+    ci = inputs.cycle_inputs(3, n_frames=1)
+    g = ci.grid
+    S, m = 4, 70
+    r = inputs.rng(12)
+    d2s, sites, cs, refs = [], [], [], []
+    rad = r.uniform(0.02, 0.2, size=m).astype(np.float32)
+    for j in range(S):
+        occ = inputs.random_grid(g.shape, 0.0005 * j, 60 + j)   # map 0 is empty
+        d2, site = oracle_lib.edt(occ)
+        C = np.concatenate([r.uniform(-0.1, 2.7, size=(m - 2, 3)),
+                            [[0.005, 0.005, 0.005], [2.555, 2.555, 1.275]]]).astype(np.float32)
+        d2s.append(to_dev(d2.ravel()))
+        sites.append(to_dev(site.ravel()))
+        cs.append(C)
+        refs.append(oracle_lib.query_spheres(g, d2, site, C, rad))
+    out = torch.full((S, m, edt.SPHERE_RESULT_WORDS), -1, dtype=torch.int32, device=dev())
+    edt.edt_query_spheres_many(g, d2s, sites, to_dev(np.stack(cs)), to_dev(rad), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    for j in range(S):
+        assert np.array_equal(got[j], refs[j]), j

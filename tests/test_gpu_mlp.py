@@ -302,3 +302,78 @@ def test_surrogate_gain_with_zero_misses():
         f"fallback {need.mean():.3f}, truly near {truly_near.mean():.3f}, misses {misses}")
     assert misses == 0
     assert skipped > 0.15
+
+
+def test_select_keeps_bits():
+    """sdf_mlp_select copies the exact record word of every flagged state and
+    the prediction of every other state, bit for bit, reading the records in
+    place through their strides (and in place over y)."""
+    g = inputs.rng(30)
+    b = 37
+    y_np = g.normal(0, 10, (b, 12)).astype(np.float32)
+    rec_np = g.integers(-2**31, 2**31 - 1, (b, 12, 16), dtype=np.int64).astype(np.int32)
+    need_np = (g.random(b) < 0.5).astype(np.int32) * g.integers(1, 9, b).astype(np.int32)
+    y = torch.from_numpy(y_np).to(dev())
+    rec = torch.from_numpy(rec_np).to(dev())
+    need = torch.from_numpy(need_np).to(dev())
+    out = torch.full((b, 12), -1.0, dtype=torch.float32, device=dev())
+    exact = rec[:, :, 6].view(torch.float32)
+    mlp.sdf_mlp_select(y, need, exact, out)
+    torch.cuda.synchronize()
+    ref = np.where(need_np[:, None] != 0, rec_np[:, :, 6], y_np.view(np.int32))
+    assert np.array_equal(out.cpu().numpy().view(np.int32), ref)
+    mlp.sdf_mlp_select(y, need, exact, y)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy().view(np.int32), ref)
+    assert 0 < (need_np != 0).sum() < b
+
+
+def test_assisted_lookahead_graph(oracle_lib):
+    """The look-ahead batch with no host round trip (one graph: forward,
+    fallback flags, gated exact transform, select): the flags follow the
+    oracle's rule on the predictions, every flagged state gets the oracle's
+    exact distances, every other state its prediction, over several
+    replays whose flags differ (so switched-off slots hold stale maps)."""
+    from paper_2407_02363_amd.selfmap import SelfMapLabeler
+    from paper_2407_02363_amd.surrogate import AssistedLookahead
+    st = inputs.self_map_setup()
+    g = st.grid
+    S, chunks = 16, 3
+    sur = perturbed_surrogate(31)
+    sur.eps.fill_(0.5)
+    radii = torch.from_numpy(st.sphere_radii).to(dev())
+    lab = SelfMapLabeler(st, chunk=S, device=dev(), use_graph=False)
+    qs = inputs.random_joint_states(chunks * S, 32)
+    poses, cen = lab.stage(qs)
+    q = torch.from_numpy(qs.astype(np.float32)).to(dev())
+    ws = mlp.new_workspace(S, dev())
+    preds = []
+    for k in range(chunks):
+        y = torch.empty((S, 12), dtype=torch.float32, device=dev())
+        mlp.sdf_mlp_forward(sur.w16, sur.master, q[k * S:(k + 1) * S], y, ws)
+        preds.append(y.cpu().numpy())
+    pred = np.concatenate(preds)
+    eps_np = sur.eps.cpu().numpy()
+    slack = (pred.astype(np.float64) * g.voxel - st.sphere_radii[None] - eps_np[None] * g.voxel).min(1)
+    margin = float(np.median(slack))
+    assist = AssistedLookahead(sur, lab, radii, g.voxel, margin)
+    flagged = 0
+    for k in range(chunks):
+        sl = slice(k * S, (k + 1) * S)
+        say(f"[assisted] chunk {k}")
+        out = assist.run(q[sl], poses[sl], cen[sl]).cpu().numpy()
+        need = assist.need.cpu().numpy().astype(bool)
+        ref_need = M.needs_exact(pred[sl], st.sphere_radii, g.voxel, margin, eps_np)
+        assert np.array_equal(need, ref_need), k
+        assert int(assist.count.item()) == int(need.sum())
+        assert np.array_equal(out[~need].view(np.int32), pred[sl][~need].view(np.int32)), k
+        for j in np.flatnonzero(need):
+            qj = qs[k * S + j]
+            occ = np.zeros(g.shape, np.uint8)
+            oracle_lib.insert_links(g, occ, st.link_pts, st.link_off, st.robot.poses12(qj), st.mask)
+            d2, site = oracle_lib.edt(occ)
+            c = inputs.sphere_centres(st.robot, qj, st.sphere_links, st.sphere_local)
+            ref = oracle_lib.query_spheres(g, d2, site, c, st.sphere_radii).view(np.float32)[:, 6]
+            assert np.array_equal(out[j].view(np.int32), ref.view(np.int32)), (k, j)
+        flagged += int(need.sum())
+    assert 0 < flagged < chunks * S
