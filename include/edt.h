@@ -201,7 +201,7 @@ int edt_update_logodds(const edt_grid_t* grid, int16_t* logodds, uint8_t* occ, c
  * 2^-48), so they do not depend on the order of accumulation; keep[i] = 1
  * iff point i is finite and d_i <= mu + alpha * sigma (double).  The
  * neighbour search is exact for coordinates within about 80 m of the
- * sensor origin (cells of 1.001 radius).
+ * sensor origin (cells of 1.001 radius / 2).
  *   pts        device float32 [n][3], sensor frame; n <= EDT_OUTLIER_MAX_POINTS
  *   radius     metres, > 0; n * radius^2 must stay below 32,000 m^2 (and
  *              n * radius below 8e6 m) so that the exact sums cannot overflow

@@ -98,6 +98,28 @@ def test_edge_cases():
     assert (d == np.float32(0.01)).all() and (k == 1).all() and st[1] < 1e-7
 
 
+def test_clusters_sharing_table_buckets():
+    """Clusters that the neighbour-search table folds onto the same buckets,
+    and runs of cells that wrap round the table: the search wraps its grid
+    of cells (half the radius) with a period of 16 cells per axis for 1,020
+    points, so clusters 16 cells apart share buckets and a cluster around the
+    origin straddles the wrap.  Every d_i and keep decision
+    against the all-pairs oracle."""
+    R = 0.01
+    period = 16 * np.float32(R * 0.5005)
+    g = inputs.rng(44)
+    base = g.uniform(-0.012, 0.012, (250, 3)).astype(np.float32)
+    shifts = [(0, 0, 0), (period, 0, 0), (0, period, period), (-period, -2 * period, 0)]
+    p = np.concatenate([base + np.float32(s) for s in [np.array(v, np.float32) for v in shifts]])
+    p = np.concatenate([p, g.uniform(-0.2, 0.2, (20, 3)).astype(np.float32)])
+    say(f"[outlier] folded clusters: {p.shape[0]} points")
+    gk, gd, gs = gpu_filter(p, k=8, radius=R, alpha=0.5)
+    rk, rd, rs = oracle.outlier_filter(p, k=8, radius=R, alpha=0.5)
+    assert np.array_equal(gd, rd), np.flatnonzero(gd != rd)[:5]
+    assert gs == rs and np.array_equal(gk, rk)
+    assert 0 < rk.sum() < p.shape[0]
+
+
 def test_filtered_frame_feeds_logodds_update():
     ci = inputs.cycle_inputs(9, n_frames=1, grid=inputs.Grid(96, 80, 48, (0.7, 0.6, 0.0), 0.025))
     g = ci.grid
