@@ -677,6 +677,14 @@ def main():
     for k in range(args.warmup):
         cyc.run(k)
     torch.cuda.synchronize()
+    # the autotuner's tiles for this map shape; its cache then serves every
+    # transform of the run
+    heuristic_tiles = edt.edt_default_tuning(g)
+    tuned_tiles, tuned_us = edt.edt_autotune(g, cyc.occ_env, cyc.d2_env, cyc.site_env, reps=20)
+    log(f"[bench] autotune: tiles {tuned_tiles} ({tuned_us:.1f} us), heuristic {heuristic_tiles}")
+    autotune = {"tiles": list(tuned_tiles), "heuristic_tiles": list(heuristic_tiles),
+                "transform_us_while_tuning": tuned_us,
+                "fields": "xy_tile, z_tile, z_group, xy_group"}
 
     def run_steps(fn, n):
         torch.cuda.synchronize()
@@ -850,7 +858,7 @@ def main():
            "timing": mode, "latency": latency, "h2d_frame": h2d,
            "cycle_variants": variants, "occupancy": occupancy, "static_scene": static_scene,
            "edt_comparison": comparison, "closed_loop": closed_loop, "large_map": large_map,
-           "edt_only": edt_only, "kernels": kernels, "roofline": roofline,
+           "edt_only": edt_only, "autotune": autotune, "kernels": kernels, "roofline": roofline,
            "batched": batched, "surrogate": surrogate,
            "paper_context": {"edt_ms": 3.9767, "mvox_s": 2109, "hw": "GTX 1080 Ti",
                              "workload": "live camera scene, 256x256x128 at 1 cm"}}

@@ -451,6 +451,33 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
                          int32_t reps, edt_tuning_t* best, float* best_us, void* stream);
 
 /*
+ * The tile choices of edt_autotune and edt_autotune_batched are cached in the
+ * process per device architecture (the part of the HIP architecture name
+ * before any ':', e.g. "gfx950") and shape: edt_compute and
+ * edt_compute_many use the cached tiles of a map's shape on a device of that
+ * architecture, edt_compute_batched those of a batch's map count and largest
+ * extents.  The cache can be written to a text file and read back by a later
+ * process, so that autotuning runs once per machine type and shape:
+ *   edt_tuning_cache_save  writes every entry to path (overwriting it);
+ *                          returns the number of entries written.
+ *   edt_tuning_cache_load  adds the file's entries to the cache (an entry for
+ *                          the same architecture and shape is replaced);
+ *                          returns the number of entries read.  A file that
+ *                          is not a cache, or any line that is not a valid
+ *                          entry (tiles the library cannot launch for that
+ *                          shape), fails with EDT_ERR_ARG and adds nothing.
+ *   edt_tuning_cache_clear forgets every entry (the heuristic tiles apply).
+ * File format: the line "edtmi tuning cache v1", then one entry per line,
+ *   single <arch> <nx> <ny> <nz> xy <xy_tile> <xy_group> z <z_tile> <z_group>
+ *   batch <arch> <maps> <nx> <ny> <nz> xy <xy_tile> <xy_group> z <z_tile> <z_group>
+ * blank lines and lines starting with '#' ignored.  Host-only calls; no GPU
+ * is needed to save or load.
+ */
+int edt_tuning_cache_save(const char* path);
+int edt_tuning_cache_load(const char* path);
+int edt_tuning_cache_clear(void);
+
+/*
  * edt_query_spheres -- closest obstacle at bounding-sphere centres
  * (Alg. 2 ExtractClosestObstaclePose; task variable x_c of Eq. dist and the
  * constraint x_c >= radius of Eq. ref).

@@ -156,9 +156,6 @@ int make_plan(const edt_batch_map_t* maps, int n, int txy, int tz, BatchPlan& p)
     return EDT_OK;
 }
 
-std::mutex g_batch_mu;
-std::map<std::tuple<int, int, int, int>, EdtTuning> g_batch_tuned;
-
 EdtTuning batch_default(int nx, int ny, int nz)
 {
     edt_grid_t g{nx, ny, nz, {0.0f, 0.0f, 0.0f}, 1.0f};
@@ -170,9 +167,8 @@ EdtTuning batch_default(int nx, int ny, int nz)
 
 EdtTuning batch_current(int n, int nx, int ny, int nz)
 {
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    auto it = g_batch_tuned.find(std::make_tuple(n, nx, ny, nz));
-    return it != g_batch_tuned.end() ? it->second : batch_default(nx, ny, nz);
+    EdtTuning t;
+    return tuned_lookup(1, n, nx, ny, nz, t) ? t : batch_default(nx, ny, nz);
 }
 
 template <int TXY, int TZ>
@@ -429,10 +425,7 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
         ny = std::max(ny, maps[i].grid.ny);
         nz = std::max(nz, maps[i].grid.nz);
     }
-    {
-        std::lock_guard<std::mutex> lk(g_batch_mu);
-        g_batch_tuned[std::make_tuple(n_maps, nx, ny, nz)] = bt;
-    }
+    tuned_store(1, n_maps, nx, ny, nz, bt);
     if (best) {
         best->xy_tile = bt.xy_tw;
         best->z_tile = bt.z_tw;

@@ -57,6 +57,11 @@ inline EdtTuning tuning_from(const edt_tuning_t* p)
 }
 EdtTuning default_tuning(const edt_grid_t* g);   // heuristic
 EdtTuning current_tuning(const edt_grid_t* g);   // autotuned if cached, else heuristic
+// The autotuners' choices, per device architecture: single maps (kind 0) by
+// (nx, ny, nz), batches (kind 1) by (maps, largest nx, ny, nz).  Lookups
+// and stores use the current device's architecture.
+bool tuned_lookup(int kind, int n, int nx, int ny, int nz, EdtTuning& out);
+void tuned_store(int kind, int n, int nx, int ny, int nz, const EdtTuning& t);
 bool tile_ok(int pass, int tw, const edt_grid_t* g, int nt);   // pass 1 = xy, 2 = z
 bool needs_wide(const edt_grid_t* g);
 // The xy pass of one map into xy (the site buffer); d2 may serve as scratch.

@@ -1,20 +1,47 @@
-// Autotuner of the EDT tile widths (the band parameters of Alg. 1).
+// Autotuner of the EDT tile widths (the band parameters of Alg. 1), and the
+// cache of its choices.
 //
 // Every valid (xy_tile, z_tile) pair is timed on a representative map with
 // HIP events; the pass times are independent, so the best pair is the best
-// xy tile with the best z tile.  The winner is cached per grid shape for the
-// life of the process and used by edt_compute.
+// xy tile with the best z tile.  The winner is cached per device
+// architecture and grid shape and used by edt_compute; the cache can be
+// written to a text file and read back by a later process.
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
+#include <vector>
 
 #include "common.h"
 
 namespace edtmi {
 
 namespace {
+// (architecture, kind, maps, nx, ny, nz) -> tiles
+using TuneKey = std::tuple<std::string, int, int, int, int, int>;
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, EdtTuning> g_tuned;
+std::map<TuneKey, EdtTuning> g_tuned;
+
+// The current device's architecture name without its feature suffixes
+// ("gfx950"), "" when there is no device.
+std::string current_arch()
+{
+    constexpr int MAX_DEV = 64;
+    static std::string names[MAX_DEV];
+    static std::once_flag once[MAX_DEV];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return std::string();
+    std::call_once(once[dev], [dev]() {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            std::string a = prop.gcnArchName;
+            names[dev] = a.substr(0, a.find(':'));
+        }
+    });
+    return names[dev];
+}
 
 const int XY_TILES[] = {16, 32, 64};
 const int XY_GROUPS[] = {256, 512};
@@ -60,12 +87,42 @@ int time_pass(const edt_grid_t* g, const uint8_t* occ, int32_t* d2, int32_t* sit
 }
 }  // namespace
 
+bool tuned_lookup(int kind, int n, int nx, int ny, int nz, EdtTuning& out)
+{
+    const std::string arch = current_arch();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(TuneKey{arch, kind, n, nx, ny, nz});
+    if (it == g_tuned.end()) return false;
+    out = it->second;
+    return true;
+}
+
+void tuned_store(int kind, int n, int nx, int ny, int nz, const EdtTuning& t)
+{
+    const std::string arch = current_arch();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[TuneKey{arch, kind, n, nx, ny, nz}] = t;
+}
+
 EdtTuning current_tuning(const edt_grid_t* g)
 {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(std::make_tuple(g->nx, g->ny, g->nz));
-    return it != g_tuned.end() ? it->second : default_tuning(g);
+    EdtTuning t;
+    return tuned_lookup(0, 0, g->nx, g->ny, g->nz, t) ? t : default_tuning(g);
 }
+
+namespace {
+constexpr const char* CACHE_HEADER = "edtmi tuning cache v1";
+
+// A cache line's tiles are ones the library can launch for its shape.
+bool entry_ok(int kind, int n, int nx, int ny, int nz, const EdtTuning& t)
+{
+    edt_grid_t g{nx, ny, nz, {0.0f, 0.0f, 0.0f}, 1.0f};
+    if (check_grid(&g)) return false;
+    if (kind == 0) return n == 0 && tile_ok(1, t.xy_tw, &g, t.xy_nt) && tile_ok(2, t.z_tw, &g, t.z_nt);
+    return n >= 1 && n <= EDT_BATCH_MAX && (t.xy_tw == 16 || t.xy_tw == 32) &&
+           (t.z_tw == 16 || t.z_tw == 32 || t.z_tw == 64) && t.xy_nt == 256 && t.z_nt == 256;
+}
+}  // namespace
 
 }  // namespace edtmi
 
@@ -123,10 +180,7 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
         set_error("edt_autotune: no valid tile for this grid");
         return EDT_ERR_UNSUPPORTED;
     }
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = EdtTuning{bxy, bz, bnt, bxnt};
-    }
+    tuned_store(0, 0, grid->nx, grid->ny, grid->nz, EdtTuning{bxy, bz, bnt, bxnt});
     // leave a complete transform in d2 / site
     rc = launch_edt_xy(grid, occ, d2, reinterpret_cast<uint32_t*>(site), bxy, bxnt, st);
     if (!rc) rc = launch_edt_z(grid, d2, site, bz, bnt, st);
@@ -142,6 +196,111 @@ int edt_autotune(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, int32_
         best->xy_group = bxnt;
     }
     if (best_us) *best_us = 1000.0f * (best_xy + best_z);
+    return EDT_OK;
+}
+
+int edt_tuning_cache_save(const char* path)
+{
+    if (!path) {
+        set_error("edt_tuning_cache_save: path is NULL");
+        return EDT_ERR_ARG;
+    }
+    std::vector<std::pair<TuneKey, EdtTuning>> all;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        all.assign(g_tuned.begin(), g_tuned.end());
+    }
+    FILE* f = std::fopen(path, "w");
+    if (!f) {
+        set_error("edt_tuning_cache_save: cannot open %s for writing", path);
+        return EDT_ERR_ARG;
+    }
+    std::fprintf(f, "%s\n", CACHE_HEADER);
+    for (const auto& e : all) {
+        const TuneKey& k = e.first;
+        const EdtTuning& t = e.second;
+        if (std::get<1>(k) == 0)
+            std::fprintf(f, "single %s %d %d %d xy %d %d z %d %d\n", std::get<0>(k).c_str(), std::get<3>(k),
+                         std::get<4>(k), std::get<5>(k), t.xy_tw, t.xy_nt, t.z_tw, t.z_nt);
+        else
+            std::fprintf(f, "batch %s %d %d %d %d xy %d %d z %d %d\n", std::get<0>(k).c_str(), std::get<2>(k),
+                         std::get<3>(k), std::get<4>(k), std::get<5>(k), t.xy_tw, t.xy_nt, t.z_tw, t.z_nt);
+    }
+    const bool ok = std::fflush(f) == 0;
+    std::fclose(f);
+    if (!ok) {
+        set_error("edt_tuning_cache_save: writing %s failed", path);
+        return EDT_ERR_ARG;
+    }
+    return (int)all.size();
+}
+
+int edt_tuning_cache_load(const char* path)
+{
+    if (!path) {
+        set_error("edt_tuning_cache_load: path is NULL");
+        return EDT_ERR_ARG;
+    }
+    FILE* f = std::fopen(path, "r");
+    if (!f) {
+        set_error("edt_tuning_cache_load: cannot open %s", path);
+        return EDT_ERR_ARG;
+    }
+    std::vector<std::pair<TuneKey, EdtTuning>> got;
+    char line[512];
+    int lineno = 0, rc = EDT_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        const size_t len = std::strlen(line);
+        if (len + 1 == sizeof line && line[len - 1] != '\n') {
+            set_error("edt_tuning_cache_load: %s:%d: line too long", path, lineno);
+            rc = EDT_ERR_ARG;
+            break;
+        }
+        if (lineno == 1) {
+            if (std::strncmp(line, CACHE_HEADER, std::strlen(CACHE_HEADER)) != 0) {
+                set_error("edt_tuning_cache_load: %s is not a tuning cache (first line)", path);
+                rc = EDT_ERR_ARG;
+                break;
+            }
+            continue;
+        }
+        if (line[0] == '\n' || line[0] == '#') continue;
+        char kind[16] = "", arch[64] = "";
+        int n = 0, nx, ny, nz, consumed = 0;
+        EdtTuning t{};
+        bool ok = false;
+        if (std::sscanf(line, "%15s %63s", kind, arch) == 2) {
+            if (!std::strcmp(kind, "single"))
+                ok = std::sscanf(line, "single %*s %d %d %d xy %d %d z %d %d %n", &nx, &ny, &nz, &t.xy_tw,
+                                 &t.xy_nt, &t.z_tw, &t.z_nt, &consumed) == 7;
+            else if (!std::strcmp(kind, "batch"))
+                ok = std::sscanf(line, "batch %*s %d %d %d %d xy %d %d z %d %d %n", &n, &nx, &ny, &nz,
+                                 &t.xy_tw, &t.xy_nt, &t.z_tw, &t.z_nt, &consumed) == 8;
+        }
+        const int k = !std::strcmp(kind, "batch") ? 1 : 0;
+        if (!ok || line[consumed] != '\0' || !entry_ok(k, n, nx, ny, nz, t)) {
+            set_error("edt_tuning_cache_load: %s:%d: not a valid entry", path, lineno);
+            rc = EDT_ERR_ARG;
+            break;
+        }
+        got.emplace_back(TuneKey{arch, k, n, nx, ny, nz}, t);
+    }
+    if (!rc && lineno == 0) {
+        set_error("edt_tuning_cache_load: %s is empty", path);
+        rc = EDT_ERR_ARG;
+    }
+    std::fclose(f);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : got) g_tuned[e.first] = e.second;
+    return (int)got.size();
+}
+
+int edt_tuning_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
     return EDT_OK;
 }
 

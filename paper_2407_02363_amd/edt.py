@@ -71,7 +71,8 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_cache_workspace_bytes", "edt_cache_reset", "edt_compute_cached",
             "edt_jfa_workspace_bytes", "edt_jfa",
             "edt_autotune_batched", "edt_compute_batched_noalloc", "edt_compute_many_gated",
-            "edt_clear_insert_links_many", "edt_query_spheres_many"]
+            "edt_clear_insert_links_many", "edt_query_spheres_many", "edt_tuning_cache_save",
+            "edt_tuning_cache_load", "edt_tuning_cache_clear"]
 
 BATCH_MAX = 48
 
@@ -101,6 +102,9 @@ def lib():
         "edt_query_spheres": ([G, P, P, P, P, i32, P, P], ctypes.c_int),
         "edt_clear_insert_links_many": ([G, P, i32, P, P, i32, P, u64, P, P], ctypes.c_int),
         "edt_query_spheres_many": ([G, P, P, i32, P, P, i32, P, P], ctypes.c_int),
+        "edt_tuning_cache_save": ([ctypes.c_char_p], ctypes.c_int),
+        "edt_tuning_cache_load": ([ctypes.c_char_p], ctypes.c_int),
+        "edt_tuning_cache_clear": ([], ctypes.c_int),
         "edt_compute_stage": ([G, P, P, P, ctypes.c_int, ctypes.POINTER(Tuning), P], ctypes.c_int),
         "edt_default_tuning": ([G, ctypes.POINTER(Tuning)], ctypes.c_int),
         "edt_compute_tuned": ([G, P, P, P, ctypes.POINTER(Tuning), P], ctypes.c_int),
@@ -247,6 +251,24 @@ def edt_query_spheres_many(grid, d2s, sites, centres, radii, out, stream=None):
         _dev(centres, torch.float32, "centres", 3 * m * k), _dev(radii, torch.float32, "radii", m), m,
         _dev(out, torch.int32, "out", SPHERE_RESULT_WORDS * m * k), _stream(stream)),
         "edt_query_spheres_many")
+
+
+def edt_tuning_cache_save(path) -> int:
+    """Write the autotuners' cached tiles to a text file; returns the entry count."""
+    rc = lib().edt_tuning_cache_save(os.fsencode(path))
+    _check(min(rc, 0), "edt_tuning_cache_save")
+    return rc
+
+
+def edt_tuning_cache_load(path) -> int:
+    """Add a saved cache's entries; returns the entry count."""
+    rc = lib().edt_tuning_cache_load(os.fsencode(path))
+    _check(min(rc, 0), "edt_tuning_cache_load")
+    return rc
+
+
+def edt_tuning_cache_clear():
+    _check(lib().edt_tuning_cache_clear(), "edt_tuning_cache_clear")
 
 
 def edt_workspace_bytes(grid) -> int:

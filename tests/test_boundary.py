@@ -137,3 +137,53 @@ def test_host_validation_rejects_bad_arguments(lib):
                                  ctypes.byref(edt.Tuning(64, 8)), None) == -5
     assert lib.edt_compute_stage(ctypes.byref(ok), one, one, one, 4, None, None) == -1
     assert lib.edt_autotune(ctypes.byref(ok), one, one, one, 0, None, None, None) == -1
+
+
+CACHE_LINES = ["single gfx950 256 256 128 xy 64 512 z 64 256",
+               "batch gfx950 32 256 256 128 xy 32 256 z 64 256",
+               "single gfx942 512 512 512 xy 32 512 z 16 256"]
+
+
+def test_tuning_cache_file_round_trip(lib, tmp_path):
+    """The autotuners' cache is written to and read from a text file on the
+    host: a saved file holds exactly the loaded entries, a reloaded one gives
+    them back, and a file with any invalid line adds nothing."""
+    from paper_2407_02363_amd import edt
+    edt.edt_tuning_cache_clear()
+    src = tmp_path / "cache.txt"
+    src.write_text("edtmi tuning cache v1\n# tiles per architecture\n" + CACHE_LINES[0] + "\n\n" +
+                   "\n".join(CACHE_LINES[1:]) + "\n")
+    assert edt.edt_tuning_cache_load(src) == 3
+    out = tmp_path / "saved.txt"
+    assert edt.edt_tuning_cache_save(out) == 3
+    lines = out.read_text().splitlines()
+    assert lines[0] == "edtmi tuning cache v1" and sorted(lines[1:]) == sorted(CACHE_LINES)
+    edt.edt_tuning_cache_clear()
+    empty = tmp_path / "empty.txt"
+    assert edt.edt_tuning_cache_save(empty) == 0
+    assert empty.read_text() == "edtmi tuning cache v1\n"
+    assert edt.edt_tuning_cache_load(out) == 3
+    bad = {
+        "header": "edtmi tuning cache v2\n" + CACHE_LINES[0] + "\n",
+        "xy tile": "edtmi tuning cache v1\nsingle gfx950 256 256 128 xy 128 512 z 64 256\n",
+        "z group": "edtmi tuning cache v1\nsingle gfx950 256 256 128 xy 64 512 z 64 1024\n",
+        "grid": "edtmi tuning cache v1\nsingle gfx950 0 256 128 xy 64 512 z 64 256\n",
+        "maps": "edtmi tuning cache v1\nbatch gfx950 49 256 256 128 xy 32 256 z 64 256\n",
+        "batch tile": "edtmi tuning cache v1\nbatch gfx950 4 256 256 128 xy 64 256 z 64 256\n",
+        "trailing": "edtmi tuning cache v1\nsingle gfx950 256 256 128 xy 64 512 z 64 256 7\n",
+        "short": "edtmi tuning cache v1\nsingle gfx950 256 256 xy 64 512 z 64 256\n",
+        "kind": "edtmi tuning cache v1\ndouble gfx950 256 256 128 xy 64 512 z 64 256\n",
+        "empty": "",
+    }
+    for name, text in bad.items():
+        f = tmp_path / f"bad_{name.replace(' ', '_')}.txt"
+        # a valid line after the invalid one must not be added either
+        good_then_bad = text if name in ("header", "empty") else text + CACHE_LINES[1] + "\n"
+        f.write_text(good_then_bad)
+        edt.edt_tuning_cache_clear()
+        with pytest.raises(edt.EdtError):
+            edt.edt_tuning_cache_load(f)
+        assert edt.edt_tuning_cache_save(empty) == 0, name
+    with pytest.raises(edt.EdtError):
+        edt.edt_tuning_cache_load(tmp_path / "missing.txt")
+    edt.edt_tuning_cache_clear()

@@ -211,6 +211,41 @@ def test_autotune_keeps_results(oracle_lib):
     assert np.array_equal(site.cpu().numpy().reshape(occ.shape), rsite)
 
 
+def test_autotuned_tiles_survive_a_saved_cache(oracle_lib, tmp_path):
+    """The autotuner's choice goes into the cache under this device's
+    architecture, a saved cache restores it after the cache is cleared (the
+    heuristic tiles apply in between), and the transform with the restored
+    tiles is exact."""
+    import torch
+    from paper_2407_02363_amd import edt
+    from tests.gpu_util import dev, grid_of
+    occ = inputs.boxes_grid(48, seed=4)
+    g = grid_of(occ.shape)
+    o = torch.from_numpy(occ.ravel()).to(dev())
+    d2 = torch.empty(occ.size, dtype=torch.int32, device=dev())
+    site = torch.empty_like(d2)
+    edt.edt_tuning_cache_clear()
+    heuristic = edt.edt_default_tuning(g)
+    tiles, _ = edt.edt_autotune(g, o, d2, site, reps=2)
+    path = tmp_path / "tiles.txt"
+    assert edt.edt_tuning_cache_save(path) == 1
+    line = path.read_text().splitlines()[1].split()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    assert line[:5] == ["single", arch, "48", "48", "48"], line
+    assert (int(line[6]), int(line[9]), int(line[10]), int(line[7])) == tiles
+    edt.edt_tuning_cache_clear()
+    assert edt.edt_default_tuning(g) == heuristic
+    assert edt.edt_tuning_cache_load(path) == 1
+    assert edt.edt_default_tuning(g) == tiles
+    d2.fill_(-1)
+    edt.edt_compute(g, o, d2, site)
+    torch.cuda.synchronize()
+    rd2, rsite = oracle_lib.edt(occ)
+    assert np.array_equal(d2.cpu().numpy().reshape(occ.shape), rd2)
+    assert np.array_equal(site.cpu().numpy().reshape(occ.shape), rsite)
+    edt.edt_tuning_cache_clear()
+
+
 def test_cached_transform_skips_only_unchanged_maps(oracle_lib):
     """edt_compute_cached: the first call and every call after a change give
     the oracle's result; a call on an unchanged map (occupied / free
