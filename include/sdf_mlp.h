@@ -123,6 +123,22 @@ int sdf_mlp_fallback(const float* y, const float* radii, const float* eps_vox, i
                      float voxel, float margin, int32_t* need, int32_t* count, void* stream);
 
 /*
+ * sdf_mlp_infer -- sdf_mlp_forward for inference: the same predictions, bit
+ * for bit, in one launch (one work-group per 64 states, the activations kept
+ * on chip), with no workspace and nothing kept for a backward pass.
+ *   q     float32 [batch][7] joint angles, radians, device.
+ *   y     float32 [batch][12] out, voxels, device.
+ *   need  int32 [batch] out (nullable): when given, the fallback rule of
+ *         sdf_mlp_fallback is applied to y with radii, eps_vox, voxel and
+ *         margin (same arguments, same float32 evaluation, same decisions);
+ *         its count is not produced.  radii and eps_vox may be NULL when
+ *         need is.
+ */
+int sdf_mlp_infer(const uint16_t* w16, const float* master, const float* q, int32_t batch, float* y,
+                  const float* radii, const float* eps_vox, float voxel, float margin, int32_t* need,
+                  void* stream);
+
+/*
  * sdf_mlp_select -- the distances a look-ahead batch ends with: the exact
  * ones for the states that needed the exact self-map transform, the
  * predictions for the rest.  For every state b and sphere i:

@@ -297,6 +297,106 @@ __global__ void k_encode(const float* __restrict__ q, int n_rows, const int* __r
     x[i] = f2bf(v);
 }
 
+// The whole forward pass for inference, one 512-thread work-group per 64
+// rows of the batch: the encoded input and the hidden activations stay in
+// LDS (row stride HID + 8 bf16) and the weights come from L2.  Wave w owns
+// the output columns [32 w, 32 w + 32) of a layer; it loads its weight rows
+// for every K step at once and then runs its products, only over the 16-row
+// tiles that hold states.  Every product is the same sequence of
+// v_mfma_f32_16x16x32_bf16 over K in steps of 32 as in k_gemm, with the same
+// epilogues, so y is bit-identical to sdf_mlp_forward's.  With need given,
+// the work-group also applies k_fallback's rule to its rows.
+constexpr int INF_LD = HID + 8;
+
+__global__ __launch_bounds__(512) void k_mlp_infer(const uint16_t* __restrict__ w16,
+                                                   const float* __restrict__ master,
+                                                   const float* __restrict__ q, int batch,
+                                                   float* __restrict__ y, const float* __restrict__ radii,
+                                                   const float* __restrict__ eps, float voxel, float margin,
+                                                   int* __restrict__ need)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t act[2][64 * INF_LD];
+    __shared__ float yout[64 * SDF_MLP_OUT];
+    const int t = threadIdx.x;
+    const int wave = t >> 6;
+    const int lane = t & 63;
+    const int row0 = blockIdx.x * 64;
+    const int rows = min(64, batch - row0);
+    const int mt = (rows + 15) >> 4;   // 16-row tiles that hold states
+    // encode: [sin q1, cos q1, ..., sin q7, cos q7, 0 ...] as bf16 (k_encode's values)
+    for (int i = t; i < 64 * INP; i += 512) {
+        const int b = i / INP, c = i % INP;
+        float v = 0.0f;
+        if (b < rows && c < 2 * SDF_MLP_JOINTS) {
+            const float a = q[(size_t)(row0 + b) * SDF_MLP_JOINTS + (c >> 1)];
+            v = (c & 1) ? cosf(a) : sinf(a);
+        }
+        act[0][b * INF_LD + c] = f2bf(v);
+    }
+    __syncthreads();
+    const int r = lane & 15;
+    const int kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const uint16_t* A = act[l & 1];
+        uint16_t* O = act[(l & 1) ^ 1];
+        constexpr int KS_MAX = HID / 32;
+        const int K = l == 0 ? INP : HID;
+        const int N = l == 3 ? OUTP : HID;
+        const uint16_t* W = w16 + (l == 0 ? SDF_MLP_W1 : l == 1 ? SDF_MLP_W2 : l == 2 ? SDF_MLP_W3 : SDF_MLP_W4);
+        const float* bias = master + (l == 0 ? SDF_MLP_B1 : l == 1 ? SDF_MLP_B2 : l == 2 ? SDF_MLP_B3 : SDF_MLP_B4);
+        const int n0 = wave * 32;
+        if (n0 < N) {
+            bf16x8 b[2][KS_MAX];
+#pragma unroll
+            for (int ks = 0; ks < KS_MAX; ++ks)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    if (ks * 32 < K)
+                        b[j][ks] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                                                  W + (size_t)(n0 + 16 * j + r) * K + ks * 32 + kq));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i >= mt) break;
+                f32x4 acc[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+                for (int ks = 0; ks < KS_MAX; ++ks) {
+                    if (ks * 32 >= K) break;
+                    const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                                                    A + (16 * i + r) * INF_LD + ks * 32 + kq));
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j][ks], acc[j], 0, 0, 0);
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = 16 * i + 4 * (lane >> 4) + e;
+                        const int n = n0 + 16 * j + r;
+                        const float z = acc[j][e] + bias[n];
+                        if (l < 3) {
+                            O[m * INF_LD + n] = f2bf((z > 0.0f || z != z) ? z : 0.0f);
+                        } else if (n < SDF_MLP_OUT && m < rows) {
+                            y[(size_t)(row0 + m) * SDF_MLP_OUT + n] = z;
+                            yout[m * SDF_MLP_OUT + n] = z;
+                        }
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    if (need && t < rows) {
+        int flag = 0;
+        for (int i = 0; i < SDF_MLP_OUT; ++i) {
+            const float c = yout[t * SDF_MLP_OUT + i] * voxel - radii[i];
+            const float thresh = margin + eps[i] * voxel;
+            if (!(c >= thresh)) flag = 1;   // NaN predictions also fall back
+        }
+        need[row0 + t] = flag;
+    }
+}
+
 // y32 [P][32] -> y [batch][12]
 __global__ void k_copy_out(const float* __restrict__ y32, int batch, float* __restrict__ y)
 {
@@ -640,6 +740,23 @@ int sdf_mlp_fallback(const float* y, const float* radii, const float* eps_vox, i
     hipLaunchKernelGGL(k_fallback, dim3((batch + 255) / 256), dim3(256), 0, st, y, radii, eps_vox,
                        (int)batch, voxel, margin, need, count);
     return check_launch("k_fallback");
+}
+
+int sdf_mlp_infer(const uint16_t* w16, const float* master, const float* q, int32_t batch, float* y,
+                  const float* radii, const float* eps_vox, float voxel, float margin, int32_t* need,
+                  void* stream)
+{
+    if (!w16 || !master || !q || !y || batch < 1) {
+        set_error("sdf_mlp_infer: NULL pointer or batch < 1");
+        return EDT_ERR_ARG;
+    }
+    if (need && (!radii || !eps_vox || !(voxel > 0.0f))) {
+        set_error("sdf_mlp_infer: the fallback rule needs radii, eps_vox and a voxel size > 0");
+        return EDT_ERR_ARG;
+    }
+    hipLaunchKernelGGL(k_mlp_infer, dim3((batch + 63) / 64), dim3(512), 0, as_stream(stream), w16, master, q,
+                       (int)batch, y, radii, eps_vox, voxel, margin, need);
+    return check_launch("k_mlp_infer");
 }
 
 int sdf_mlp_select(const float* y, const int32_t* need, const float* exact, int32_t exact_row,

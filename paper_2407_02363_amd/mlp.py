@@ -21,7 +21,7 @@ LAYOUT = [(W1, B1, N_HIDDEN, IN_PAD), (W2, B2, N_HIDDEN, N_HIDDEN), (W3, B3, N_H
 REAL = [(N_HIDDEN, N_IN), (N_HIDDEN, N_HIDDEN), (N_HIDDEN, N_HIDDEN), (N_OUT, N_HIDDEN)]
 
 EXPORTED = ["sdf_mlp_workspace_bytes", "sdf_mlp_pack", "sdf_mlp_forward", "sdf_mlp_backward",
-            "sdf_mlp_adam", "sdf_mlp_fallback", "sdf_mlp_calibrate", "sdf_mlp_select"]
+            "sdf_mlp_adam", "sdf_mlp_fallback", "sdf_mlp_calibrate", "sdf_mlp_select", "sdf_mlp_infer"]
 _sig_done = False
 
 
@@ -39,6 +39,7 @@ def lib():
             "sdf_mlp_fallback": ([P, P, P, i32, f, f, P, P, P], ctypes.c_int),
             "sdf_mlp_calibrate": ([P, P, i32, f, P, P], ctypes.c_int),
             "sdf_mlp_select": ([P, P, P, i32, i32, i32, P, P], ctypes.c_int),
+            "sdf_mlp_infer": ([P, P, P, i32, P, P, P, f, f, P, P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -87,6 +88,20 @@ def sdf_mlp_forward(w16, master, q, y, ws, idx=None, stream=None):
                                  _dev(q, torch.float32, "q", JOINTS * rows), rows, _idx(idx, b), b,
                                  None if y is None else _dev(y, torch.float32, "y", N_OUT * b),
                                  _ptr(ws), ws.numel(), _stream(stream)), "sdf_mlp_forward")
+
+
+def sdf_mlp_infer(w16, master, q, y, radii=None, eps_vox=None, voxel=0.0, margin=0.0, need=None,
+                  stream=None):
+    """Predictions y float32 [B, 12] for q float32 [B, 7], one launch; with
+    need (int32 [B]) also the fallback rule's decisions."""
+    b = _rows(q, JOINTS, "q")
+    _check(lib().sdf_mlp_infer(_dev(w16, torch.bfloat16, "w16", PARAMS),
+                               _dev(master, torch.float32, "master", PARAMS),
+                               _dev(q, torch.float32, "q", JOINTS * b), b,
+                               _dev(y, torch.float32, "y", N_OUT * b),
+                               _dev(radii, torch.float32, "radii", N_OUT),
+                               _dev(eps_vox, torch.float32, "eps_vox", N_OUT), float(voxel), float(margin),
+                               _dev(need, torch.int32, "need", b), _stream(stream)), "sdf_mlp_infer")
 
 
 def sdf_mlp_backward(w16, target, grad, loss, ws, idx=None, clip_vox=0.0, stream=None):

@@ -76,12 +76,12 @@ class Surrogate:
         return hist
 
     def predict(self, q, out=None):
-        """Predicted distances (voxels) float32 [N, 12] for q float32 [N, 7]."""
+        """Predicted distances (voxels) float32 [N, 12] for q float32 [N, 7]
+        (the one-launch inference kernel; the same bits as the forward pass)."""
         n = q.shape[0]
         y = out if out is not None else torch.empty((n, mlp.N_OUT), dtype=torch.float32, device=self.dev)
-        for s0 in range(0, n, self.batch):
-            k = min(self.batch, n - s0)
-            mlp.sdf_mlp_forward(self.w16, self.master, q[s0:s0 + k], y[s0:s0 + k], self.ws)
+        if n:
+            mlp.sdf_mlp_infer(self.w16, self.master, q, y)
         return y
 
     def calibrate(self, q, target):
@@ -122,8 +122,9 @@ class Surrogate:
 
 class AssistedLookahead:
     """One look-ahead batch of S joint states with no host round trip: the
-    surrogate predicts every state's sphere distances, sdf_mlp_fallback marks
-    the states it cannot clear, the labeler's gated transform runs the exact
+    surrogate predicts every state's sphere distances and, in the same launch
+    (sdf_mlp_infer), marks by the fallback rule the states it cannot clear;
+    the labeler's gated transform runs the exact
     self-map EDT for those states only (the others' work-groups return at
     once), and sdf_mlp_select keeps the exact distances of the marked states
     and the predictions of the rest.  The whole batch is one HIP graph.
@@ -145,8 +146,6 @@ class AssistedLookahead:
         self.q = torch.zeros((S, mlp.JOINTS), dtype=torch.float32, device=d)
         self.y = torch.empty((S, mlp.N_OUT), dtype=torch.float32, device=d)
         self.out = torch.empty((S, mlp.N_OUT), dtype=torch.float32, device=d)
-        self.count = torch.zeros(1, dtype=torch.int32, device=d)
-        self.ws = mlp.new_workspace(S, d)
         self.need = labeler.gate[:S]
         self.graph = None
         if use_graph:
@@ -160,15 +159,15 @@ class AssistedLookahead:
 
     def _body(self):
         s = self.sur
-        mlp.sdf_mlp_forward(s.w16, s.master, self.q, self.y, self.ws)
-        mlp.sdf_mlp_fallback(self.y, self.radii, s.eps, self.voxel, self.margin, self.need, self.count)
+        mlp.sdf_mlp_infer(s.w16, s.master, self.q, self.y, self.radii, s.eps, self.voxel, self.margin,
+                          self.need)
         self.lab.run_chunk(self.S, gated=True)
         mlp.sdf_mlp_select(self.y, self.need, self.lab.exact_view(self.S), self.out)
 
     def run(self, q, poses, centres):
         """q float32 [S, 7], poses / centres as SelfMapLabeler.stage gives
         them (device).  Returns the [S, 12] distances (voxels, device); need
-        (int32 [S]) and count hold which states took the exact path."""
+        (int32 [S]) holds which states took the exact path."""
         self.q.copy_(q)
         self.lab.poses[:self.S].copy_(poses)
         self.lab.centres[:self.S].copy_(centres)
