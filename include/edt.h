@@ -496,19 +496,38 @@ int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* 
                       edt_sphere_result_t* out, void* stream);
 
 /*
- * edt_query_spheres_many -- edt_query_spheres for a batch of maps of one
- * grid in one launch (the m bounding spheres at every look-ahead state).
- *   d2, site  HOST arrays of n_maps (1..EDT_BATCH_MAX) device pointers, read
- *             during the call: the outputs of the transform of map j.
- *   centres   float32 [n_maps][m][3] device: state j's sphere centres.
- *   radii     float32 [m] device, shared by every state.
- *   out       edt_sphere_result_t [n_maps][m] device.
- * Record (j, k) is exactly what edt_query_spheres gives for map j, centre
- * k.
+ * edt_query_spheres_many -- edt_query_spheres for every map of a batch in one
+ * launch (the bounding spheres of every look-ahead state, or of every map of
+ * a batched cycle).
+ *   maps      HOST array of n_maps (1..EDT_BATCH_MAX) descriptors, read during
+ *             the call: grid, d2 and site of map j (occ unused).
+ *   centres, radii, out  HOST arrays of n_maps device pointers: map j's
+ *             float32 [m[j]][3] centres, float32 [m[j]] radii and
+ *             edt_sphere_result_t [m[j]] results.
+ *   m         HOST int32 [n_maps]: spheres per map (0 allowed).
+ * Record k of map j is exactly what edt_query_spheres gives for map j,
+ * centre k.
  */
-int edt_query_spheres_many(const edt_grid_t* grid, const int32_t* const* d2,
-                           const int32_t* const* site, int32_t n_maps, const float* centres,
-                           const float* radii, int32_t m, edt_sphere_result_t* out, void* stream);
+int edt_query_spheres_many(const edt_batch_map_t* maps, int32_t n_maps, const float* const* centres,
+                           const float* const* radii, const int32_t* m, edt_sphere_result_t* const* out,
+                           void* stream);
+
+/*
+ * edt_clear_insert_points_many -- ClearMap followed by Insert(Point_Cloud) of
+ * Alg. 2 (as edt_clear, then edt_insert_points without an exclusion mask)
+ * for every map of a batch, each with its own grid, cloud and sensor pose, in
+ * two launches for the whole batch.
+ *   grids         HOST array of n_maps (1..EDT_BATCH_MAX) grids.
+ *   occ           HOST array of n_maps device pointers: map j's occupancy.
+ *   pts, T_map_sensor  HOST arrays of device pointers: map j's float32
+ *                 [n_pts[j]][3] cloud (sensor frame) and float32 [12] pose.
+ *   n_pts         HOST int64 [n_maps]: points per map (0 allowed).
+ * Each map ends exactly as edt_clear + edt_insert_points leave it.  Maps must
+ * not overlap.
+ */
+int edt_clear_insert_points_many(const edt_grid_t* grids, uint8_t* const* occ, int32_t n_maps,
+                                 const float* const* pts, const int64_t* n_pts,
+                                 const float* const* T_map_sensor, void* stream);
 
 #ifdef __cplusplus
 }

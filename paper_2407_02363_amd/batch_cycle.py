@@ -1,10 +1,13 @@
 """Batched control cycle over many maps of uneven size, through the C-ABI.
 
 Per cycle and map: ClearMap, insert that map's point cloud, the exact EDT,
-and the sphere query at every look-ahead joint state's sphere centres (one
-query launch per map for all states).  Two ways to run the EDT of the batch:
+and the sphere query at every look-ahead joint state's sphere centres; the
+clear and insertion of every map is one pair of launches and the queries of
+every map one launch (batched_io, the default), or one launch per map and
+step.  Three ways to run the EDT of the batch:
 
-  run_plain    one edt_compute per map (two kernels per map)
+  run_plain    one edt_compute per map (two kernels per map), and the clear,
+               insertion and queries one launch per map as well
   run_batched  one edt_compute_batched for all maps (one persistent launch)
   run_many     one edt_compute_many for all maps (one launch per pass)
 
@@ -19,9 +22,12 @@ from . import edt
 
 
 class BatchCycle:
-    def __init__(self, bi, device="cuda:0"):
-        """bi: inputs.BatchInputs."""
+    def __init__(self, bi, device="cuda:0", batched_io: bool = True):
+        """bi: inputs.BatchInputs.  batched_io: clear, insert and query every
+        map in one launch each (edt_clear_insert_points_many,
+        edt_query_spheres_many); False: one launch per map and step."""
         self.bi = bi
+        self.batched_io = batched_io
         self.dev = torch.device(device)
         d = self.dev
         self.grids = list(bi.grids)
@@ -47,21 +53,28 @@ class BatchCycle:
     def queries(self) -> int:
         return sum(r.numel() for r in self.radii)
 
-    def _insert(self, stream=None):
+    def _insert(self, stream=None, batched=None):
+        if self.batched_io if batched is None else batched:
+            edt.edt_clear_insert_points_many(self.grids, self.occ, self.clouds, self.T, stream)
+            return
         for g, o, c, t in zip(self.grids, self.occ, self.clouds, self.T):
             edt.edt_clear(g, o, stream)
             edt.edt_insert_points(g, o, c, t, stream=stream)
 
-    def _query(self, stream=None):
+    def _query(self, stream=None, batched=None):
+        if self.batched_io if batched is None else batched:
+            edt.edt_query_spheres_many(self.maps, self.centres, self.radii, self.out, stream)
+            return
         for i, g in enumerate(self.grids):
             edt.edt_query_spheres(g, self.d2[i], self.site[i], self.centres[i], self.radii[i],
                                   self.out[i], stream)
 
     def run_plain(self, stream=None):
-        self._insert(stream)
+        """The per-map loop: every step one launch per map."""
+        self._insert(stream, batched=False)
         for g, o, d2, s in zip(self.grids, self.occ, self.d2, self.site):
             edt.edt_compute(g, o, d2, s, stream=stream)
-        self._query(stream)
+        self._query(stream, batched=False)
 
     def run_batched(self, stream=None):
         self._insert(stream)

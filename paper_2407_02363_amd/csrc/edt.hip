@@ -361,20 +361,64 @@ __global__ void k_query_spheres(GridArgs g, const int32_t* __restrict__ d2,
     query_sphere(g, d2, site, centres, radii, i, out);
 }
 
-struct MapFields {
+// The maps of a batched query or insertion, each with its own grid and
+// buffers, indexed by blockIdx.y (kernel arguments: at most 3.5 KiB).
+struct QueryMaps {
+    GridArgs g[EDT_BATCH_MAX];
     const int32_t* d2[EDT_BATCH_MAX];
     const int32_t* site[EDT_BATCH_MAX];
+    const float* centres[EDT_BATCH_MAX];
+    const float* radii[EDT_BATCH_MAX];
+    edt_sphere_result_t* out[EDT_BATCH_MAX];
+    int m[EDT_BATCH_MAX];
 };
 
-// Sphere k of state j is thread k of row j (blockIdx.y).
-__global__ void k_query_spheres_many(GridArgs g, MapFields f, const float* __restrict__ centres,
-                                     const float* __restrict__ radii, int m,
-                                     edt_sphere_result_t* __restrict__ out)
+// Sphere i of map j is thread i of row j (blockIdx.y).
+__global__ void k_query_spheres_many(QueryMaps q)
 {
     const int j = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    query_sphere(g, f.d2[j], f.site[j], centres + (size_t)3 * m * j, radii, i, out + (size_t)m * j);
+    if (i >= q.m[j]) return;
+    query_sphere(q.g[j], q.d2[j], q.site[j], q.centres[j], q.radii[j], i, q.out[j]);
+}
+
+struct PointMaps {
+    GridArgs g[EDT_BATCH_MAX];
+    uint8_t* occ[EDT_BATCH_MAX];
+    const float* pts[EDT_BATCH_MAX];
+    const float* T[EDT_BATCH_MAX];
+    int64_t n[EDT_BATCH_MAX];      // points of map j
+    int64_t nvox[EDT_BATCH_MAX];   // voxels of map j
+};
+
+// Zero every map of the batch: 16-byte stores over each map's aligned body,
+// bytes for its head and tail.
+__global__ void k_clear_maps(PointMaps p)
+{
+    const int j = blockIdx.y;
+    uint8_t* o = p.occ[j];
+    const int64_t n = p.nvox[j];
+    const int64_t head = min(n, (int64_t)((16 - (reinterpret_cast<uintptr_t>(o) & 15)) & 15));
+    const int64_t body = (n - head) >> 4;
+    const int64_t tail = n - head - 16 * body;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < body) reinterpret_cast<uint4*>(o + head)[i] = make_uint4(0, 0, 0, 0);
+    if (i < head) o[i] = 0;
+    if (i < tail) o[head + 16 * body + i] = 0;
+}
+
+// Point i of map j's cloud, placed by map j's sensor pose.
+__global__ void k_insert_points_maps(PointMaps p)
+{
+    const int j = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n[j]) return;
+    const float* T = p.T[j];
+    float t[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) t[k] = T[k];
+    const float* q = p.pts[j];
+    insert_point(p.g[j], t, q[3 * i], q[3 * i + 1], q[3 * i + 2], p.occ[j], nullptr);
 }
 
 GridArgs grid_args(const edt_grid_t* g)
@@ -805,31 +849,74 @@ int edt_compute_cached(const edt_grid_t* grid, const uint8_t* occ, int32_t* d2, 
     return check_launch("k_cache_end");
 }
 
-int edt_query_spheres_many(const edt_grid_t* grid, const int32_t* const* d2,
-                           const int32_t* const* site, int32_t n_maps, const float* centres,
-                           const float* radii, int32_t m, edt_sphere_result_t* out, void* stream)
+int edt_query_spheres_many(const edt_batch_map_t* maps, int32_t n_maps, const float* const* centres,
+                           const float* const* radii, const int32_t* m, edt_sphere_result_t* const* out,
+                           void* stream)
 {
-    int rc = check_grid(grid);
-    if (rc) return rc;
-    if (!d2 || !site || n_maps < 1 || n_maps > EDT_BATCH_MAX || m < 0 ||
-        (m > 0 && (!centres || !radii || !out))) {
-        set_error("edt_query_spheres_many: bad pointer, %d maps outside 1..%d or negative count", n_maps,
-                  EDT_BATCH_MAX);
+    if (!maps || !centres || !radii || !m || !out || n_maps < 1 || n_maps > EDT_BATCH_MAX) {
+        set_error("edt_query_spheres_many: NULL array or %d maps outside 1..%d", n_maps, EDT_BATCH_MAX);
         return EDT_ERR_ARG;
     }
-    MapFields f;
+    static thread_local QueryMaps q;   // 3.5 KiB: off the stack
+    int m_max = 0;
     for (int j = 0; j < n_maps; ++j) {
-        if (!d2[j] || !site[j]) {
-            set_error("edt_query_spheres_many: d2[%d] or site[%d] is NULL", j, j);
+        int rc = check_grid(&maps[j].grid);
+        if (rc) return rc;
+        if (m[j] < 0 || (m[j] > 0 && (!maps[j].d2 || !maps[j].site || !centres[j] || !radii[j] || !out[j]))) {
+            set_error("edt_query_spheres_many: map %d: NULL buffer or negative count", j);
             return EDT_ERR_ARG;
         }
-        f.d2[j] = d2[j];
-        f.site[j] = site[j];
+        q.g[j] = grid_args(&maps[j].grid);
+        q.d2[j] = maps[j].d2;
+        q.site[j] = maps[j].site;
+        q.centres[j] = centres[j];
+        q.radii[j] = radii[j];
+        q.out[j] = out[j];
+        q.m[j] = m[j];
+        m_max = std::max(m_max, (int)m[j]);
     }
-    if (m == 0) return EDT_OK;
-    hipLaunchKernelGGL(k_query_spheres_many, dim3((m + 63) / 64, n_maps), dim3(64), 0, as_stream(stream),
-                       grid_args(grid), f, centres, radii, m, out);
+    if (m_max == 0) return EDT_OK;
+    hipLaunchKernelGGL(k_query_spheres_many, dim3((m_max + 63) / 64, n_maps), dim3(64), 0, as_stream(stream), q);
     return check_launch("k_query_spheres_many");
+}
+
+int edt_clear_insert_points_many(const edt_grid_t* grids, uint8_t* const* occ, int32_t n_maps,
+                                 const float* const* pts, const int64_t* n_pts,
+                                 const float* const* T_map_sensor, void* stream)
+{
+    if (!grids || !occ || !pts || !n_pts || !T_map_sensor || n_maps < 1 || n_maps > EDT_BATCH_MAX) {
+        set_error("edt_clear_insert_points_many: NULL array or %d maps outside 1..%d", n_maps, EDT_BATCH_MAX);
+        return EDT_ERR_ARG;
+    }
+    static thread_local PointMaps p;   // 3.2 KiB: off the stack
+    int64_t n_max = 0, v_max = 0;
+    for (int j = 0; j < n_maps; ++j) {
+        int rc = check_grid(&grids[j]);
+        if (rc) return rc;
+        if (!occ[j] || n_pts[j] < 0 || (n_pts[j] > 0 && (!pts[j] || !T_map_sensor[j]))) {
+            set_error("edt_clear_insert_points_many: map %d: NULL buffer or negative count", j);
+            return EDT_ERR_ARG;
+        }
+        if (n_pts[j] > (int64_t)INT_MAX * 256) {
+            set_error("edt_clear_insert_points_many: map %d: too many points", j);
+            return EDT_ERR_ARG;
+        }
+        p.g[j] = grid_args(&grids[j]);
+        p.occ[j] = occ[j];
+        p.pts[j] = pts[j];
+        p.T[j] = T_map_sensor[j];
+        p.n[j] = n_pts[j];
+        p.nvox[j] = grid_voxels(&grids[j]);
+        n_max = std::max(n_max, n_pts[j]);
+        v_max = std::max(v_max, p.nvox[j]);
+    }
+    const hipStream_t st = as_stream(stream);
+    const int64_t threads = std::max<int64_t>(v_max >> 4, 16);
+    hipLaunchKernelGGL(k_clear_maps, dim3((unsigned)((threads + 255) / 256), n_maps), dim3(256), 0, st, p);
+    int rc = check_launch("k_clear_maps");
+    if (rc || n_max == 0) return rc;
+    hipLaunchKernelGGL(k_insert_points_maps, dim3((unsigned)((n_max + 255) / 256), n_maps), dim3(256), 0, st, p);
+    return check_launch("k_insert_points_maps");
 }
 
 int edt_query_spheres(const edt_grid_t* grid, const int32_t* d2, const int32_t* site,

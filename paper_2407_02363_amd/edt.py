@@ -71,7 +71,8 @@ EXPORTED = ["edt_status_string", "edt_last_error", "edt_version", "edt_clear",
             "edt_cache_workspace_bytes", "edt_cache_reset", "edt_compute_cached",
             "edt_jfa_workspace_bytes", "edt_jfa",
             "edt_autotune_batched", "edt_compute_batched_noalloc", "edt_compute_many_gated",
-            "edt_clear_insert_links_many", "edt_query_spheres_many", "edt_tuning_cache_save",
+            "edt_clear_insert_links_many", "edt_query_spheres_many", "edt_clear_insert_points_many",
+            "edt_tuning_cache_save",
             "edt_tuning_cache_load", "edt_tuning_cache_clear"]
 
 BATCH_MAX = 48
@@ -101,7 +102,8 @@ def lib():
         "edt_compute": ([G, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "edt_query_spheres": ([G, P, P, P, P, i32, P, P], ctypes.c_int),
         "edt_clear_insert_links_many": ([G, P, i32, P, P, i32, P, u64, P, P], ctypes.c_int),
-        "edt_query_spheres_many": ([G, P, P, i32, P, P, i32, P, P], ctypes.c_int),
+        "edt_query_spheres_many": ([P, i32, P, P, P, P, P], ctypes.c_int),
+        "edt_clear_insert_points_many": ([G, P, i32, P, P, P, P], ctypes.c_int),
         "edt_tuning_cache_save": ([ctypes.c_char_p], ctypes.c_int),
         "edt_tuning_cache_load": ([ctypes.c_char_p], ctypes.c_int),
         "edt_tuning_cache_clear": ([], ctypes.c_int),
@@ -238,19 +240,49 @@ def edt_clear_insert_links_many(grid, occs, link_pts, link_off, link_poses, link
         _dev(gates, torch.int32, "gates", k), _stream(stream)), "edt_clear_insert_links_many")
 
 
-def edt_query_spheres_many(grid, d2s, sites, centres, radii, out, stream=None):
-    """Sphere queries of several maps of one grid: centres float32 device
-    [n_maps, m, 3], radii [m], out int32 device [n_maps, m, 16]."""
-    g = make_grid(grid)
-    m = radii.numel()
-    k = len(d2s)
-    d2_arr = ptr_array(d2s, torch.int32, "d2", _n(g))
-    site_arr = ptr_array(sites, torch.int32, "site", _n(g))
-    _check(lib().edt_query_spheres_many(
-        ctypes.byref(g), ctypes.cast(d2_arr, ctypes.c_void_p), ctypes.cast(site_arr, ctypes.c_void_p), k,
-        _dev(centres, torch.float32, "centres", 3 * m * k), _dev(radii, torch.float32, "radii", m), m,
-        _dev(out, torch.int32, "out", SPHERE_RESULT_WORDS * m * k), _stream(stream)),
-        "edt_query_spheres_many")
+def edt_query_spheres_many(maps, centres, radii, outs, stream=None):
+    """Sphere queries of every map of a batch in one launch: maps from
+    batch_maps() (grid, d2, site), and per map a float32 device [m, 3]
+    centres tensor, a float32 [m] radii tensor and an int32 [m, 16] output."""
+    k = len(maps)
+    if not (len(centres) == len(radii) == len(outs) == k):
+        raise ValueError("one centres, radii and out tensor per map")
+    ms = (ctypes.c_int32 * k)()
+    c_arr, r_arr, o_arr = (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)()
+    for j in range(k):
+        m = radii[j].numel()
+        ms[j] = m
+        c_arr[j] = _dev(centres[j], torch.float32, f"centres[{j}]", 3 * m).value
+        r_arr[j] = _dev(radii[j], torch.float32, f"radii[{j}]", m).value
+        o_arr[j] = _dev(outs[j], torch.int32, f"out[{j}]", SPHERE_RESULT_WORDS * m).value
+    _check(lib().edt_query_spheres_many(ctypes.cast(maps, ctypes.c_void_p), k, ctypes.cast(c_arr, ctypes.c_void_p),
+                                        ctypes.cast(r_arr, ctypes.c_void_p), ctypes.cast(ms, ctypes.c_void_p),
+                                        ctypes.cast(o_arr, ctypes.c_void_p), _stream(stream)),
+           "edt_query_spheres_many")
+
+
+def edt_clear_insert_points_many(grids, occs, clouds, poses, stream=None):
+    """Clear every map, then insert map j's cloud (float32 device [n_j, 3],
+    sensor frame) placed by poses[j] (float32 device [12])."""
+    k = len(grids)
+    if not (len(occs) == len(clouds) == len(poses) == k):
+        raise ValueError("one occupancy, cloud and pose per grid")
+    g_arr = (EdtGrid * k)()
+    n_arr = (ctypes.c_int64 * k)()
+    o_arr, p_arr, t_arr = (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)()
+    for j in range(k):
+        g = make_grid(grids[j])
+        g_arr[j] = g
+        n = clouds[j].shape[0] if clouds[j].dim() == 2 else clouds[j].numel() // 3
+        n_arr[j] = n
+        o_arr[j] = _dev(occs[j], torch.uint8, f"occ[{j}]", _n(g)).value
+        p_arr[j] = _dev(clouds[j], torch.float32, f"pts[{j}]", 3 * n).value
+        t_arr[j] = _dev(poses[j], torch.float32, f"T[{j}]", 12).value
+    _check(lib().edt_clear_insert_points_many(g_arr, ctypes.cast(o_arr, ctypes.c_void_p), k,
+                                              ctypes.cast(p_arr, ctypes.c_void_p),
+                                              ctypes.cast(n_arr, ctypes.c_void_p),
+                                              ctypes.cast(t_arr, ctypes.c_void_p), _stream(stream)),
+           "edt_clear_insert_points_many")
 
 
 def edt_tuning_cache_save(path) -> int:

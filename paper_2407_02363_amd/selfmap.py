@@ -84,8 +84,8 @@ class SelfMapLabeler:
             edt.edt_compute_many(self.maps[k], stream=stream)
         else:
             edt.edt_compute_batched(self.maps[k], self.ws, stream=stream)
-        edt.edt_query_spheres_many(g, self.d2[:k], self.site[:k], self.centres[:k], self.radii,
-                                   self.out[:k], stream)
+        edt.edt_query_spheres_many(self.maps[k], [self.centres[j] for j in range(k)], [self.radii] * k,
+                                   [self.out[j] for j in range(k)], stream)
 
     def exact_view(self, k):
         """dist_vox of the last run's first k slots: float32 [k, m] view of

@@ -173,27 +173,68 @@ def test_clear_insert_links_many(oracle_lib):
 
 
 def test_query_spheres_many(oracle_lib):
-    """One launch for the sphere queries of several maps of one grid: record
-    (j, k) equals the oracle's query of map j at centre k, inside, outside and
-    on the border of the map, and on an empty map."""
-    ci = inputs.cycle_inputs(3, n_frames=1)
-    g = ci.grid
-    S, m = 4, 70
+    """One launch for the sphere queries of several maps, each with its own
+    grid, centres, radii and count: record (j, k) equals the oracle's query of
+    map j at centre k, inside, outside and on the border of the map, on an
+    empty map, and with a map that has no spheres."""
     r = inputs.rng(12)
-    d2s, sites, cs, refs = [], [], [], []
-    rad = r.uniform(0.02, 0.2, size=m).astype(np.float32)
-    for j in range(S):
-        occ = inputs.random_grid(g.shape, 0.0005 * j, 60 + j)   # map 0 is empty
+    shapes = [(128, 256, 256), (40, 70, 130), (16, 9, 300), (64, 64, 64), (8, 8, 8)]
+    counts = [70, 33, 5, 0, 64]
+    grids, maps_occ, d2s, sites, cs, rs, outs, refs = [], [], [], [], [], [], [], []
+    for j, (sh, m) in enumerate(zip(shapes, counts)):
+        g = inputs.Grid(sh[2], sh[1], sh[0], (0.1 * j, -0.2, 0.05), 0.01 + 0.002 * j)
+        occ = inputs.random_grid(sh, 0.0005 * j, 60 + j)   # map 0 is empty
         d2, site = oracle_lib.edt(occ)
-        C = np.concatenate([r.uniform(-0.1, 2.7, size=(m - 2, 3)),
-                            [[0.005, 0.005, 0.005], [2.555, 2.555, 1.275]]]).astype(np.float32)
+        ext = np.array([g.nx, g.ny, g.nz]) * g.voxel
+        C = (np.array(g.origin) + r.uniform(-0.1, 1.1, size=(m, 3)) * ext).astype(np.float32)
+        if m >= 2:
+            C[-2:] = np.array(g.origin, np.float32) + np.float32(0.5 * g.voxel)
+            C[-1] += (ext - g.voxel).astype(np.float32)
+        rad = r.uniform(0.02, 0.2, size=m).astype(np.float32)
+        grids.append(g)
+        maps_occ.append(to_dev(occ.ravel()))
         d2s.append(to_dev(d2.ravel()))
         sites.append(to_dev(site.ravel()))
-        cs.append(C)
+        cs.append(to_dev(C.reshape(m, 3)))
+        rs.append(to_dev(rad))
+        outs.append(torch.full((max(m, 1), edt.SPHERE_RESULT_WORDS), -1, dtype=torch.int32, device=dev()))
         refs.append(oracle_lib.query_spheres(g, d2, site, C, rad))
-    out = torch.full((S, m, edt.SPHERE_RESULT_WORDS), -1, dtype=torch.int32, device=dev())
-    edt.edt_query_spheres_many(g, d2s, sites, to_dev(np.stack(cs)), to_dev(rad), out)
+    maps = edt.batch_maps(grids, maps_occ, d2s, sites)
+    edt.edt_query_spheres_many(maps, cs, rs, [o[:max(c, 0) or 1] for o, c in zip(outs, counts)])
     torch.cuda.synchronize()
-    got = out.cpu().numpy().view(np.uint32)
-    for j in range(S):
-        assert np.array_equal(got[j], refs[j]), j
+    for j, m in enumerate(counts):
+        got = outs[j].cpu().numpy().view(np.uint32)
+        if m:
+            assert np.array_equal(got[:m], refs[j]), j
+        else:
+            assert (got == 0xFFFFFFFF).all(), "a map without spheres is left alone"
+
+
+def test_clear_insert_points_many(oracle_lib):
+    """One clear launch and one insertion launch for maps of different grids,
+    clouds and poses (an empty cloud among them): every map equals the
+    oracle's ClearMap + Insert(Point_Cloud) of its own cloud, whatever it
+    held before, at odd byte offsets."""
+    shapes = [(128, 96, 200), (64, 64, 64), (40, 70, 130), (9, 300, 16)]
+    grids, occs, clouds, poses, refs = [], [], [], [], []
+    buf = torch.full((sum(int(np.prod(sh)) + 3 for sh in shapes) + 16,), 0xAB, dtype=torch.uint8, device=dev())
+    off = 1
+    for j, sh in enumerate(shapes):
+        ci = inputs.cycle_inputs(j, n_frames=1, grid=inputs.Grid(sh[2], sh[1], sh[0], (1.0, 0.9, 0.0), 0.02))
+        g = ci.grid
+        pts = ci.frames[0][::(j + 1) * 3] if j != 1 else np.zeros((0, 3), np.float32)
+        ref = np.zeros(g.shape, np.uint8)
+        oracle_lib.insert_points(g, ref, pts, ci.T_map_cam)
+        n = g.n
+        grids.append(g)
+        occs.append(buf[off:off + n])
+        off += n + 3
+        clouds.append(to_dev(np.ascontiguousarray(pts, np.float32).reshape(-1, 3)))
+        poses.append(to_dev(np.asarray(ci.T_map_cam, np.float32)))
+        refs.append(ref)
+    say(f"[points many] {len(shapes)} maps, {sum(c.shape[0] for c in clouds)} points")
+    edt.edt_clear_insert_points_many(grids, occs, clouds, poses)
+    torch.cuda.synchronize()
+    for j, g in enumerate(grids):
+        assert np.array_equal(occs[j].cpu().numpy().reshape(g.shape), refs[j]), j
+    assert refs[0].any() and not refs[1].any()
