@@ -25,8 +25,8 @@
 //            slice's row records (step 1) and a mask of its non-empty rows;
 //            a band's build visits only the non-empty rows, computing x' of
 //            its column from the record.  The band envelopes merge in a
-//            pairwise tree (4, 2, 1 seams per column); each band queries its
-//            own rows.
+//            pairwise tree (4, 2, 1 seams per column), the merged chain is
+//            moved together, and each band queries its own rows.
 #include "edt_tiles.h"
 
 namespace edtmi {
@@ -507,9 +507,9 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
     if (band == 4) merge(0, 4, 8);
     __syncthreads();
 
-    // ---- queries of rows [y0, y1): entry j of the merged chain lies in the
-    // band whose cumulative range holds j
-    if (y0 >= y1) return;
+    // ---- the merged chain made contiguous: band b's surviving entries move
+    // to [cum[b], cum[b + 1]) of the column (all read before any is written),
+    // so that the queries index the chain directly
     int lo[XY_NB], cum[XY_NB + 1];
     cum[0] = 0;
 #pragma unroll
@@ -518,16 +518,21 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
         cum[b + 1] = cum[b] + HI[b * 64] - lo[b];
     }
     const int n = cum[XY_NB];
-    auto at = [&](int j) -> uint32_t {
-        int b = 0, off = lo[0];
+    {
+        uint32_t ev[32];
+        const int mlo = lo[band], mcnt = cum[band + 1] - cum[band];
 #pragma unroll
-        for (int k = 1; k < XY_NB; ++k)
-            if (j >= cum[k]) {
-                b = k;
-                off = lo[k] - cum[k];
-            }
-        return E(b, j + off);
-    };
+        for (int i = 0; i < 32; ++i) ev[i] = i < mcnt ? E(band, mlo + i) : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < mcnt) scol[(cum[band] + i) * 64] = ev[i];
+        __syncthreads();
+    }
+
+    // ---- queries of rows [y0, y1)
+    if (y0 >= y1) return;
+    auto at = [&](int j) -> uint32_t { return scol[j * 64]; };
     // the envelope site of y0 by binary search (f is unimodal along the chain)
     int a = 0, bb = n - 1;
     while (a < bb) {
