@@ -398,8 +398,8 @@ int edt_compute_many(const edt_batch_map_t* maps, int32_t n_maps, const edt_tuni
 int edt_compute_many_gated(const edt_batch_map_t* maps, int32_t n_maps, const int32_t* gates,
                            const edt_tuning_t* tuning, void* stream);
 
-/* Workspace bytes for a batch of n_maps (queue head, error flag, one
- * counter per map). */
+/* Workspace bytes for a batch of n_maps (queue head, error flag, two
+ * counters per map). */
 size_t edt_batch_workspace_bytes(int32_t n_maps);
 
 /*
@@ -413,7 +413,9 @@ size_t edt_batch_workspace_bytes(int32_t n_maps);
  *           batches in flight at once need two workspaces.
  *   tuning  NULL = the batch autotuner's choice for this shape class, else
  *           xy_tile in {16, 32}, z_tile in {16, 32, 64} (z_group, xy_group ignored:
- *           batches use 256-thread work-groups).
+ *           batches use 256-thread work-groups), or xy_tile = z_tile = 64: the
+ *           banded lean tiles of edt_compute (512-thread work-groups; every
+ *           axis at most 512, nz at least 1).
  * Errors: EDT_ERR_UNSUPPORTED for an axis above 512 or tiles that do not
  * fit; argument errors as for edt_compute.
  */
@@ -424,7 +426,7 @@ int edt_compute_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, s
  * edt_compute_batched_noalloc -- edt_compute_batched for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same kernels and results, with the
- * batch's workspace taken from a 256-byte array that the library holds on
+ * batch's workspace taken from a 512-byte array that the library holds on
  * every GPU it runs on until the process ends.  The call allocates nothing:
  * no hipMalloc, hipFree or allocating library routine.
  *   maps, n_maps, tuning  as for edt_compute_batched (n_maps <= EDT_BATCH_MAX,

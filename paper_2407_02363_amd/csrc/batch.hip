@@ -10,15 +10,24 @@
 // always end; they are still bounded by a spin limit, past which the tile is
 // skipped and an error flag is raised in the workspace (edt_batch_status).
 //
+// Batches whose maps all fit the lean tiles (every axis <= 512, rows of 64
+// voxels or more, up to 256 rows and 128 slices) go through a second
+// persistent kernel with three phases: the row records of every map, then
+// the lean xy tiles of every map (a map's wait for its records), then the
+// lean z tiles of every map, two per work-group (a map's wait for its xy
+// tiles).
+//
 // Workspace (unsigned words): [0] queue head, [1] error flag,
-// [2 + m] finished xy tiles of map m.  A small fill kernel zeroes it before
-// every launch, so the pair of launches can be captured into a graph.
+// [2 + m] finished record items (lean) or xy tiles (general) of map m,
+// [2 + n + m] finished xy tiles of map m (lean).  A small fill kernel zeroes
+// it before every launch, so the pair of launches can be captured into a
+// graph.
 #include <map>
 #include <mutex>
 #include <tuple>
 #include <vector>
 
-#include "edt_tiles.h"
+#include "edt_lean.h"
 
 namespace edtmi {
 
@@ -108,9 +117,179 @@ void k_edt_batched(BatchArgs a, unsigned* ws, unsigned spin_limit)
     }
 }
 
+// ---- lean batches
+struct LeanMap {
+    const uint8_t* occ;
+    int32_t* d2;
+    int32_t* site;
+    int nx, ny, nz;
+    int ntx;                 // 64-column tiles per row
+    int per;                 // record rows per wave
+    int waves;               // record waves of the map
+    int r_begin, r_count;    // queue range of its record items (8 waves each)
+    int x_begin, x_count;    // its xy tiles
+    int z_begin, z_count;    // its z items (two z tiles each)
+};
+
+struct LeanArgs {
+    int n_maps;
+    int n_r;       // record items of all maps (first in the queue)
+    int n_rx;      // record and xy items
+    int n_total;   // all items
+    LeanMap m[EDT_BATCH_MAX];
+};
+
+// Thread 0 waits until counter reaches target (acquire, device scope),
+// bounded by spin_limit; every thread learns whether it did.
+__device__ __forceinline__ bool wait_count(unsigned* ws, int counter, unsigned target, unsigned spin_limit,
+                                           int* s_ok)
+{
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(&ws[counter], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++spins > spin_limit) {
+                ok = 0;
+                atomicOr(&ws[WS_ERR], 1u);
+                break;
+            }
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// Raises counter once every thread's stores of the item are issued (release).
+__device__ __forceinline__ void release_count(unsigned* ws, int counter)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(&ws[counter], 1u);
+    }
+}
+
+// Items a work-group takes per dequeue: consecutive items (rows of one map,
+// then its neighbours), so each atomic on the queue head is shared by four
+// items.  Chunks of 2 or 4 measured best on 32 uneven maps; 16 leaves the
+// tail of the queue to a few work-groups.
+constexpr int LEAN_CHUNK = 4;
+__global__ __launch_bounds__(512) void k_edt_batched_lean(LeanArgs a, unsigned* ws, unsigned spin_limit)
+{
+    __shared__ union {
+        lean::XyLds xy;
+        lean::ZLds z[2];
+    } u;
+    __shared__ int s_item;
+    __shared__ int s_ok;
+    const int n = a.n_maps;
+    int it = 0, left = 0;
+    for (;;) {
+        __syncthreads();   // the previous item's LDS use is over
+        if (left == 0) {   // the next chunk of LEAN_CHUNK consecutive items
+            if (threadIdx.x == 0) s_item = (int)atomicAdd(&ws[WS_HEAD], 1u);
+            __syncthreads();
+            it = __builtin_amdgcn_readfirstlane(s_item) * LEAN_CHUNK;
+            left = LEAN_CHUNK;
+        } else {
+            ++it;
+        }
+        --left;
+        if (it >= a.n_total) break;
+        if (it < a.n_r) {
+            // 8 record waves: wave w of the work-group takes record wave 8 (it - r_begin) + w
+            int m = 0;
+            while (m + 1 < n && a.m[m + 1].r_begin <= it) ++m;
+            const LeanMap& d = a.m[m];
+            const int wv = __builtin_amdgcn_readfirstlane((it - d.r_begin) * 8 + (int)(threadIdx.x >> 6));
+            if (wv < d.waves) {
+                const int row0 = wv * d.per;
+                const int nrows = min(d.per, d.ny * d.nz - row0);
+                if (record_words(d.occ, d.nx))
+                    row_summary_words(d.occ, d.nx, (size_t)row0, nrows, row_records(d.d2, d.nx, d.ny, d.nz));
+                else
+                    row_summary(d.occ, d.nx, (size_t)row0, nrows, row_records(d.d2, d.nx, d.ny, d.nz));
+            }
+            release_count(ws, WS_DONE + m);
+        } else if (it < a.n_rx) {
+            int m = 0;
+            while (m + 1 < n && a.m[m + 1].x_begin <= it) ++m;
+            const LeanMap& d = a.m[m];
+            if (wait_count(ws, WS_DONE + m, (unsigned)d.r_count, spin_limit, &s_ok))
+                lean::xy_tile(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny,
+                              d.ntx, it - d.x_begin, u.xy);
+            release_count(ws, WS_DONE + n + m);
+        } else {
+            // two z tiles of one map, one per half of the work-group; a half
+            // without a tile only takes part in the barriers
+            int m = 0;
+            while (m + 1 < n && a.m[m + 1].z_begin <= it) ++m;
+            const LeanMap& d = a.m[m];
+            const bool ok = wait_count(ws, WS_DONE + n + m, (unsigned)d.x_count, spin_limit, &s_ok);
+            const int h = (int)(threadIdx.x >> 8);
+            const int tile = (it - d.z_begin) * 2 + h;
+            const bool act = ok && tile < d.ny * d.ntx;
+            lean::z_tile(d.d2, d.site, d.nx, d.ny, act ? d.nz : 0, d.ntx, act ? tile : 0, (int)(threadIdx.x & 255),
+                         u.z[h]);
+        }
+    }
+}
+
+// Every map fits the lean tiles (and has its d2 for the records).
+bool lean_batch_ok(const edt_batch_map_t* maps, int n)
+{
+    for (int i = 0; i < n; ++i) {
+        const edt_grid_t& g = maps[i].grid;
+        if (g.nx < 64 || g.nx > 512 || g.ny > lean::XY_MAX || g.nz > lean::Z_MAX || !maps[i].d2) return false;
+    }
+    return true;
+}
+
+int make_lean_plan(const edt_batch_map_t* maps, int n, LeanArgs& a)
+{
+    a.n_maps = n;
+    int q = 0;
+    for (int i = 0; i < n; ++i) {
+        const edt_grid_t& g = maps[i].grid;
+        LeanMap& d = a.m[i];
+        d.occ = maps[i].occ;
+        d.d2 = maps[i].d2;
+        d.site = maps[i].site;
+        d.nx = g.nx;
+        d.ny = g.ny;
+        d.nz = g.nz;
+        d.ntx = (g.nx + 63) / 64;
+        d.per = record_rows_per_wave(d.occ, d.nx);
+        d.waves = (g.ny * g.nz + d.per - 1) / d.per;
+        d.r_begin = q;
+        d.r_count = (d.waves + 7) / 8;
+        q += d.r_count;
+    }
+    a.n_r = q;
+    for (int i = 0; i < n; ++i) {
+        LeanMap& d = a.m[i];
+        d.x_begin = q;
+        d.x_count = d.nz * d.ntx;
+        q += d.x_count;
+    }
+    a.n_rx = q;
+    for (int i = 0; i < n; ++i) {
+        LeanMap& d = a.m[i];
+        d.z_begin = q;
+        d.z_count = (d.ny * d.ntx + 1) / 2;
+        q += d.z_count;
+    }
+    a.n_total = q;
+    return EDT_OK;
+}
+
 struct BatchPlan {
     BatchArgs args;
     int nx_max, ny_max, nz_max;
+    bool lean;
+    LeanArgs largs;
 };
 
 int make_plan(const edt_batch_map_t* maps, int n, int txy, int tz, BatchPlan& p)
@@ -165,10 +344,11 @@ EdtTuning batch_default(int nx, int ny, int nz)
     return t;
 }
 
-EdtTuning batch_current(int n, int nx, int ny, int nz)
+EdtTuning batch_current(int n, int nx, int ny, int nz, bool lean_ok)
 {
     EdtTuning t;
-    return tuned_lookup(1, n, nx, ny, nz, t) ? t : batch_default(nx, ny, nz);
+    if (tuned_lookup(1, n, nx, ny, nz, t) && (t.xy_tw != 64 || lean_ok)) return t;
+    return lean_ok ? EdtTuning{64, 64, 512, 512} : batch_default(nx, ny, nz);
 }
 
 template <int TXY, int TZ>
@@ -208,8 +388,38 @@ int launch_batched_tz(const BatchPlan& p, unsigned* ws, hipStream_t st)
     return check_launch("k_edt_batched");
 }
 
+int launch_batched_lean(const BatchPlan& p, unsigned* ws, hipStream_t st)
+{
+    static int per_cu = 0;
+    static int n_cu = 0;
+    if (!n_cu) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_edt_batched_lean),
+                                                         512, 0) != hipSuccess) {
+            n_cu = 0;
+            set_error("edt_compute_batched: device query failed");
+            return EDT_ERR_HIP;
+        }
+        if (per_cu < 1) per_cu = 1;
+    }
+    const int grid = std::max(1, std::min(p.largs.n_total, per_cu * n_cu));
+    const int nws = WS_DONE + 2 * p.largs.n_maps;
+    hipLaunchKernelGGL(k_batch_reset, dim3((nws + 63) / 64), dim3(64), 0, st, ws, nws);
+    int rc = check_launch("k_batch_reset");
+    if (rc) return rc;
+    const unsigned spin_limit = 1u << 21;   // about 0.5 s of 8-slot sleeps
+    hipLaunchKernelGGL(k_edt_batched_lean, dim3(grid), dim3(512), 0, st, p.largs, ws, spin_limit);
+    return check_launch("k_edt_batched_lean");
+}
+
+// The lean batch kernel stands for the tile pair (64, 64).
+constexpr int LEAN_TILE = 64;
+
 int launch_batched(const BatchPlan& p, int txy, int tz, unsigned* ws, hipStream_t st)
 {
+    if (txy == LEAN_TILE && tz == LEAN_TILE && p.lean) return launch_batched_lean(p, ws, st);
     if (txy == 32) {
         if (tz == 64) return launch_batched_tz<32, 64>(p, ws, st);
         if (tz == 32) return launch_batched_tz<32, 32>(p, ws, st);
@@ -241,20 +451,29 @@ int batch_common(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t w
         ny = std::max(ny, maps[i].grid.ny);
         nz = std::max(nz, maps[i].grid.nz);
     }
+    const bool lean_ok = lean_batch_ok(maps, n_maps);
     if (tuning) {
         t.xy_tw = tuning->xy_tile;
         t.z_tw = tuning->z_tile;
         t.z_nt = 256;
         t.xy_nt = 256;
     } else {
-        t = batch_current(n_maps, nx, ny, nz);
+        t = batch_current(n_maps, nx, ny, nz, lean_ok);
     }
-    if ((t.xy_tw != 16 && t.xy_tw != 32) || (t.z_tw != 16 && t.z_tw != 32 && t.z_tw != 64)) {
+    p.lean = t.xy_tw == LEAN_TILE && t.z_tw == LEAN_TILE;
+    if (p.lean && !lean_ok) {
+        set_error("edt_compute_batched: the lean tiles (64, 64) need every axis <= 512, rows of 64 voxels or "
+                  "more, at most 256 rows and 128 slices");
+        return EDT_ERR_UNSUPPORTED;
+    }
+    if (!p.lean && ((t.xy_tw != 16 && t.xy_tw != 32) || (t.z_tw != 16 && t.z_tw != 32 && t.z_tw != 64))) {
         set_error("edt_compute_batched: tiles (%d, %d) not available for batches", t.xy_tw, t.z_tw);
         return EDT_ERR_UNSUPPORTED;
     }
-    int rc = make_plan(maps, n_maps, t.xy_tw, t.z_tw, p);
+    // validates every map (the general plan's checks hold for lean batches too)
+    int rc = make_plan(maps, n_maps, p.lean ? 32 : t.xy_tw, p.lean ? 64 : t.z_tw, p);
     if (rc) return rc;
+    if (p.lean) return make_lean_plan(maps, n_maps, p.largs);
     constexpr size_t LDS_MAX = 160 * 1024 - 8192;
     if (xy_lds(t.xy_tw, p.ny_max) > LDS_MAX || z_lds(t.z_tw, p.nz_max) > LDS_MAX) {
         set_error("edt_compute_batched: tiles (%d, %d) need too much local memory", t.xy_tw, t.z_tw);
@@ -270,8 +489,8 @@ int batch_common(const edt_batch_map_t* maps, int32_t n_maps, void* ws, size_t w
 // process.  Host code never passes the symbol itself to a kernel: it takes
 // the array's device address on each device once, with that device current.
 // ---------------------------------------------------------------------------
-constexpr int SCRATCH_WORDS = 64;
-static_assert(WS_DONE + EDT_BATCH_MAX <= SCRATCH_WORDS, "scratch too small for the largest batch");
+constexpr int SCRATCH_WORDS = 128;
+static_assert(WS_DONE + 2 * EDT_BATCH_MAX <= SCRATCH_WORDS, "scratch too small for the largest batch");
 static __device__ __align__(256) unsigned scratch[SCRATCH_WORDS];
 
 constexpr int MAX_DEVICES = 64;
@@ -311,7 +530,7 @@ extern "C" {
 size_t edt_batch_workspace_bytes(int32_t n_maps)
 {
     if (n_maps < 0) n_maps = 0;
-    const size_t words = WS_DONE + (size_t)n_maps;
+    const size_t words = WS_DONE + 2 * (size_t)n_maps;
     return (words * 4 + 255) / 256 * 256;
 }
 
@@ -368,7 +587,7 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
         return EDT_ERR_ARG;
     }
     const hipStream_t st = as_stream(stream);
-    const int XY[] = {16, 32};
+    const int XY[] = {16, 32, LEAN_TILE};   // (64, 64): the lean batch kernel
     const int Z[] = {16, 32, 64};
     float best_ms = 1e30f;
     EdtTuning bt{0, 0, 256};
@@ -378,8 +597,10 @@ int edt_autotune_batched(const edt_batch_map_t* maps, int32_t n_maps, void* ws, 
         return EDT_ERR_HIP;
     }
     int rc = EDT_OK;
+    const bool lean_ok = lean_batch_ok(maps, n_maps);
     for (int txy : XY) {
         for (int tz : Z) {
+            if (txy == LEAN_TILE && (tz != LEAN_TILE || !lean_ok)) continue;
             edt_tuning_t cand{txy, tz, 256};
             BatchPlan p;
             EdtTuning t;

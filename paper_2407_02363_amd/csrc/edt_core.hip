@@ -91,7 +91,8 @@ __global__ __launch_bounds__(256) void k_edt_z_lean(EdtMapSet s)
     const int T = (int)blockIdx.x;
     const EdtMap& d = s.m[map_of(s, T)];
     if (gated_off(d)) return;
-    lean::z_tile(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin);
+    __shared__ lean::ZLds lds;
+    lean::z_tile(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, (int)threadIdx.x, lds);
 }
 
 __global__ __launch_bounds__(512) void k_edt_xy_lean(EdtMapSet s)
@@ -100,8 +101,9 @@ __global__ __launch_bounds__(512) void k_edt_xy_lean(EdtMapSet s)
     const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
     const EdtMap& d = s.m[map_of(s, T)];
     if (gated_off(d)) return;
+    __shared__ lean::XyLds lds;
     lean::xy_tile(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny,
-                  d.ntx, T - d.begin);
+                  d.ntx, T - d.begin, lds);
 }
 
 // Allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per

@@ -71,23 +71,40 @@ __device__ __forceinline__ int z_key(uint32_t e, int p)
 
 constexpr int Z_MAX = 128;   // slices a lean z tile holds
 constexpr int XY_MAX = 256;  // rows a lean xy tile holds
+constexpr int XY_NB = 8;     // bands of 32 rows of a lean xy tile
+
+// The local memory of one z tile and of one xy tile (the caller declares
+// them, so that one persistent work-group can hold either).
+struct ZLds {
+    uint32_t val[Z_MAX * 64];   // per position: K, then the linked entry
+    uint32_t msk[4 * 64];       // per band: alive positions
+};
+struct XyLds {
+    uint32_t stk[XY_NB * 32 * 64];   // [band][slot][col]: x' | y' << 16
+    uint64_t rw[XY_MAX];             // the tile's word of every row
+    int16_t rl[XY_MAX], rr[XY_MAX];  // nearest occupied column left / right of it
+    uint32_t rmask[XY_MAX / 32];     // non-empty rows
+    int16_t s_lo[XY_NB * 64], s_hi[XY_NB * 64];
+};
 
 // ---------------------------------------------------------------------------
-// z pass (step 4): tile T = y * ntx + x0 / 64 of a map with nz <= 128; the
-// work-group has 64 * ceil(nz_max / 32) threads for the largest nz of the
-// launch, and bands past this map's nz only take part in the barriers.
-// Reads the packed 2D sites from site and overwrites d2 and site in place:
-// every global read happens before the first barrier, every write after the
-// last, and a column belongs to one work-group.
+// z pass (step 4): tile T = y * ntx + x0 / 64 of a map with nz <= 128, by the
+// 64 * ceil(nz_max / 32) threads tid = 0, 1, ... of a work-group (nz_max the
+// largest nz of the launch; bands past this map's nz, or every band when
+// nz = 0, only take part in the three barriers).  Reads the packed 2D sites
+// from site and overwrites d2 and site in place: every global read happens
+// before the first barrier, every write after the last, and a column
+// belongs to one tile.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void z_tile(int32_t* d2, int32_t* site, int nx, int ny, int nz, int ntx, int T)
+__device__ __forceinline__ void z_tile(int32_t* d2, int32_t* site, int nx, int ny, int nz, int ntx, int T,
+                                       int tid, ZLds& L)
 {
-    __shared__ uint32_t val[Z_MAX * 64];   // per position: K, then the linked entry
-    __shared__ uint32_t msk[4 * 64];       // per band: alive positions
+    uint32_t* val = L.val;
+    uint32_t* msk = L.msk;
     const int y = T / ntx;
     const int x0 = (T - y * ntx) * 64;
-    const int col = threadIdx.x & 63;
-    const int band = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int col = tid & 63;
+    const int band = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int xc = x0 + col;
     const bool live = xc < nx;
     const int xl = live ? xc : nx - 1;
@@ -314,16 +331,16 @@ __device__ __forceinline__ void z_tile(int32_t* d2, int32_t* site, int nx, int n
 // from the map's row records; 512 threads.  Writes the 2D site x' | y' << 16
 // of every voxel of the tile (0xFFFFFFFF if the slice is empty).
 // ---------------------------------------------------------------------------
-constexpr int XY_NB = 8;
-
 __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restrict__ out, int nx, int ny,
-                                        int ntx, int T)
+                                        int ntx, int T, XyLds& L)
 {
-    __shared__ uint32_t stk[XY_NB * 32 * 64];   // [band][slot][col]: x' | y' << 16
-    __shared__ uint64_t rw[XY_MAX];              // the tile's word of every row
-    __shared__ int16_t rl[XY_MAX], rr[XY_MAX];   // nearest occupied column left / right of it
-    __shared__ uint32_t rmask[XY_MAX / 32];      // non-empty rows
-    __shared__ int16_t s_lo[XY_NB * 64], s_hi[XY_NB * 64];
+    uint32_t* stk = L.stk;
+    uint64_t* rw = L.rw;
+    int16_t* rl = L.rl;
+    int16_t* rr = L.rr;
+    uint32_t* rmask = L.rmask;
+    int16_t* s_lo = L.s_lo;
+    int16_t* s_hi = L.s_hi;
     const int z = T / ntx;
     const int tx = T - z * ntx;
     const int x0 = tx * 64;

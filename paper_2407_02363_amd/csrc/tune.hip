@@ -119,8 +119,9 @@ bool entry_ok(int kind, int n, int nx, int ny, int nz, const EdtTuning& t)
     edt_grid_t g{nx, ny, nz, {0.0f, 0.0f, 0.0f}, 1.0f};
     if (check_grid(&g)) return false;
     if (kind == 0) return n == 0 && tile_ok(1, t.xy_tw, &g, t.xy_nt) && tile_ok(2, t.z_tw, &g, t.z_nt);
-    return n >= 1 && n <= EDT_BATCH_MAX && (t.xy_tw == 16 || t.xy_tw == 32) &&
-           (t.z_tw == 16 || t.z_tw == 32 || t.z_tw == 64) && t.xy_nt == 256 && t.z_nt == 256;
+    const bool lean = t.xy_tw == 64 && t.z_tw == 64;   // the lean batch kernel
+    return n >= 1 && n <= EDT_BATCH_MAX && (lean || ((t.xy_tw == 16 || t.xy_tw == 32) &&
+           (t.z_tw == 16 || t.z_tw == 32 || t.z_tw == 64))) && t.xy_nt == 256 && t.z_nt == 256;
 }
 }  // namespace
 

@@ -140,7 +140,7 @@ def test_host_validation_rejects_bad_arguments(lib):
 
 
 CACHE_LINES = ["single gfx950 256 256 128 xy 64 512 z 64 256",
-               "batch gfx950 32 256 256 128 xy 32 256 z 64 256",
+               "batch gfx950 32 256 256 128 xy 64 256 z 64 256",
                "single gfx942 512 512 512 xy 32 512 z 16 256"]
 
 
@@ -169,7 +169,7 @@ def test_tuning_cache_file_round_trip(lib, tmp_path):
         "z group": "edtmi tuning cache v1\nsingle gfx950 256 256 128 xy 64 512 z 64 1024\n",
         "grid": "edtmi tuning cache v1\nsingle gfx950 0 256 128 xy 64 512 z 64 256\n",
         "maps": "edtmi tuning cache v1\nbatch gfx950 49 256 256 128 xy 32 256 z 64 256\n",
-        "batch tile": "edtmi tuning cache v1\nbatch gfx950 4 256 256 128 xy 64 256 z 64 256\n",
+        "batch tile": "edtmi tuning cache v1\nbatch gfx950 4 256 256 128 xy 64 256 z 32 256\n",
         "trailing": "edtmi tuning cache v1\nsingle gfx950 256 256 128 xy 64 512 z 64 256 7\n",
         "short": "edtmi tuning cache v1\nsingle gfx950 256 256 xy 64 512 z 64 256\n",
         "kind": "edtmi tuning cache v1\ndouble gfx950 256 256 128 xy 64 512 z 64 256\n",

@@ -52,6 +52,42 @@ def test_mixed_batch_matches_oracle(oracle_lib):
     check(occs, d2s, sites, oracle_lib, "mixed")
 
 
+def lean_batch(seed):
+    """Maps the lean batch kernel takes: rows of 64-512 voxels, up to 256 rows
+    and 128 slices, ragged, sparse to dense, one empty."""
+    shapes = [(128, 256, 256), (64, 64, 64), (97, 130, 65), (1, 40, 64), (128, 255, 200), (33, 1, 300),
+              (70, 200, 512), (5, 256, 64)]
+    dens = [0.001, 0.3, 0.01, 0.05, 0.0005, 0.02, 0.0, 0.002]
+    occs = [inputs.random_grid(sh, d, seed * 50 + i) for i, (sh, d) in enumerate(zip(shapes, dens))]
+    occs[0][3, 200, 17] = 1
+    grids = [inputs.Grid(sh[2], sh[1], sh[0]) for sh in shapes]
+    return occs, grids
+
+
+def test_lean_batch_kernel(oracle_lib):
+    """The persistent batch kernel with the lean tiles (records, xy, then z
+    tiles two per work-group, each phase waiting for the map's previous one):
+    every map against the oracle, by default and asked for as tiles (64, 64),
+    twice in a row on one workspace; asking for it on a batch it cannot take
+    is an error."""
+    occs, grids = lean_batch(1)
+    say(f"[batch] lean kernel, {len(occs)} maps")
+    for tiles in (None, (64, 64)):
+        d2s, sites, keep = run_batch(occs, grids, tiles)
+        check(occs, d2s, sites, oracle_lib, f"lean {tiles}")
+        o, d2, st, maps, ws = keep
+        for a in d2 + st:
+            a.fill_(-7)
+        edt.edt_compute_batched(maps, ws, tiles)
+        torch.cuda.synchronize()
+        assert not edt.edt_batch_status(ws)
+        check(occs, [a.cpu().numpy().reshape(x.shape) for a, x in zip(d2, occs)],
+              [a.cpu().numpy().reshape(x.shape) for a, x in zip(st, occs)], oracle_lib, f"lean again {tiles}")
+    mocc, mgrids = mixed_batch(5)
+    with pytest.raises(edt.EdtError):
+        run_batch(mocc, mgrids, (64, 64))
+
+
 @pytest.mark.parametrize("tiles", [(16, 16), (16, 32), (16, 64), (32, 16), (32, 32), (32, 64)])
 def test_every_batch_tiling(oracle_lib, tiles):
     occs, grids = mixed_batch(2)
