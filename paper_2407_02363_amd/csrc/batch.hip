@@ -136,6 +136,8 @@ struct LeanArgs {
     int n_r;       // record items of all maps (first in the queue)
     int n_rx;      // record and xy items
     int n_total;   // all items
+    int r_chunk;   // record items per dequeue
+    int t_chunk;   // xy or z items per dequeue
     LeanMap m[EDT_BATCH_MAX];
 };
 
@@ -171,11 +173,13 @@ __device__ __forceinline__ void release_count(unsigned* ws, int counter)
     }
 }
 
-// Items a work-group takes per dequeue: consecutive items (rows of one map,
-// then its neighbours), so each atomic on the queue head is shared by four
-// items.  Chunks of 2 or 4 measured best on 32 uneven maps; 16 leaves the
-// tail of the queue to a few work-groups.
-constexpr int LEAN_CHUNK = 4;
+// A work-group takes a chunk of consecutive items per dequeue: r_chunk
+// record items while the queue head h is below the number of record chunks
+// n_rc, then t_chunk tile items from item n_r + (h - n_rc) t_chunk.  The host
+// sizes the chunks so that every work-group still gets several of them:
+// chunks share one atomic and one barrier among their items on large
+// batches, and a small batch keeps one item per dequeue so that its items
+// spread over every work-group.
 __global__ __launch_bounds__(512) void k_edt_batched_lean(LeanArgs a, unsigned* ws, unsigned spin_limit)
 {
     __shared__ union {
@@ -185,14 +189,21 @@ __global__ __launch_bounds__(512) void k_edt_batched_lean(LeanArgs a, unsigned* 
     __shared__ int s_item;
     __shared__ int s_ok;
     const int n = a.n_maps;
+    const int n_rc = (a.n_r + a.r_chunk - 1) / a.r_chunk;
     int it = 0, left = 0;
     for (;;) {
         __syncthreads();   // the previous item's LDS use is over
-        if (left == 0) {   // the next chunk of LEAN_CHUNK consecutive items
+        if (left == 0) {
             if (threadIdx.x == 0) s_item = (int)atomicAdd(&ws[WS_HEAD], 1u);
             __syncthreads();
-            it = __builtin_amdgcn_readfirstlane(s_item) * LEAN_CHUNK;
-            left = LEAN_CHUNK;
+            const int h = __builtin_amdgcn_readfirstlane(s_item);
+            if (h < n_rc) {
+                it = h * a.r_chunk;
+                left = min(a.r_chunk, a.n_r - it);
+            } else {
+                it = a.n_r + (h - n_rc) * a.t_chunk;
+                left = max(1, min(a.t_chunk, a.n_total - it));
+            }
         } else {
             ++it;
         }
@@ -282,6 +293,7 @@ int make_lean_plan(const edt_batch_map_t* maps, int n, LeanArgs& a)
         q += d.z_count;
     }
     a.n_total = q;
+    a.r_chunk = a.t_chunk = 1;   // sized for the grid at launch
     return EDT_OK;
 }
 
@@ -404,13 +416,19 @@ int launch_batched_lean(const BatchPlan& p, unsigned* ws, hipStream_t st)
         }
         if (per_cu < 1) per_cu = 1;
     }
-    const int grid = std::max(1, std::min(p.largs.n_total, per_cu * n_cu));
-    const int nws = WS_DONE + 2 * p.largs.n_maps;
+    const int slots = per_cu * n_cu;
+    const int grid = std::max(1, std::min(p.largs.n_total, slots));
+    // chunks of up to 4 items once every work-group gets at least 2 record
+    // chunks and 8 tile chunks (measured on 32 uneven maps against 2 maps)
+    LeanArgs la = p.largs;
+    la.r_chunk = std::max(1, std::min(4, la.n_r / (2 * slots)));
+    la.t_chunk = std::max(1, std::min(4, (la.n_total - la.n_r) / (8 * slots)));
+    const int nws = WS_DONE + 2 * la.n_maps;
     hipLaunchKernelGGL(k_batch_reset, dim3((nws + 63) / 64), dim3(64), 0, st, ws, nws);
     int rc = check_launch("k_batch_reset");
     if (rc) return rc;
     const unsigned spin_limit = 1u << 21;   // about 0.5 s of 8-slot sleeps
-    hipLaunchKernelGGL(k_edt_batched_lean, dim3(grid), dim3(512), 0, st, p.largs, ws, spin_limit);
+    hipLaunchKernelGGL(k_edt_batched_lean, dim3(grid), dim3(512), 0, st, la, ws, spin_limit);
     return check_launch("k_edt_batched_lean");
 }
 
