@@ -95,15 +95,17 @@ __global__ __launch_bounds__(256) void k_edt_z_lean(EdtMapSet s)
     lean::z_tile(d.d2, d.site, d.nx, d.ny, d.nz, d.ntx, T - d.begin, (int)threadIdx.x, lds);
 }
 
+// Ent = uint16_t (narrow stack entries) when every map has at most 256 columns.
+template <typename Ent>
 __global__ __launch_bounds__(512) void k_edt_xy_lean(EdtMapSet s)
 {
     // as in k_edt_xy: chunks of 16 tiles per XCD, rotating over the XCDs
     const int T = xcd_chunk_remap(blockIdx.x, s.total, 16);
     const EdtMap& d = s.m[map_of(s, T)];
     if (gated_off(d)) return;
-    __shared__ lean::XyLds lds;
-    lean::xy_tile(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny,
-                  d.ntx, T - d.begin, lds);
+    __shared__ lean::XyLdsT<Ent> lds;
+    lean::xy_tile<Ent>(row_records(d.d2, d.nx, d.ny, d.nz), reinterpret_cast<uint32_t*>(d.site), d.nx, d.ny,
+                       d.ntx, T - d.begin, lds);
 }
 
 // Allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per
@@ -168,7 +170,25 @@ int launch_xy_w(const EdtMapSet& s, hipStream_t st)
     if (TW == 64 && NTX == 512 && !WIDE && lean_xy_ok(s)) {
         int rc = launch_row_records(s, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_edt_xy_lean, dim3(s.total), dim3(512), 0, st, s);
+        // narrow stack entries (maps of at most 256 columns) fit twice the
+        // work-groups per CU but cost a little more per tile: they pay only
+        // when the launch has more tiles than the wide ones keep resident
+        // (2 per CU)
+        static int n_cu = 0;
+        if (!n_cu) {
+            int dev = 0, c = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+                n_cu = c;
+            else
+                n_cu = 256;
+        }
+        int nx_max = 0;
+        for (int i = 0; i < s.n; ++i) nx_max = std::max(nx_max, s.m[i].nx);
+        if (nx_max <= 256 && s.total > 2 * n_cu)
+            hipLaunchKernelGGL(k_edt_xy_lean<uint16_t>, dim3(s.total), dim3(512), 0, st, s);
+        else
+            hipLaunchKernelGGL(k_edt_xy_lean<uint32_t>, dim3(s.total), dim3(512), 0, st, s);
         return check_launch("k_edt_xy_lean");
     }
     if (rows_first(s)) {

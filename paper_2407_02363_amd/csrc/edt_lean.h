@@ -79,13 +79,19 @@ struct ZLds {
     uint32_t val[Z_MAX * 64];   // per position: K, then the linked entry
     uint32_t msk[4 * 64];       // per band: alive positions
 };
-struct XyLds {
-    uint32_t stk[XY_NB * 32 * 64];   // [band][slot][col]: x' | y' << 16
+template <typename Ent>
+struct XyLdsT {
+    Ent stk[XY_NB * 32 * 64];        // [band][slot][col]: one envelope entry
     uint64_t rw[XY_MAX];             // the tile's word of every row
     int16_t rl[XY_MAX], rr[XY_MAX];  // nearest occupied column left / right of it
     uint32_t rmask[XY_MAX / 32];     // non-empty rows
     int16_t s_lo[XY_NB * 64], s_hi[XY_NB * 64];
 };
+// Entries x' | y' << 16 for any map; y' | |x - x'| << 8 for maps of at most
+// 256 columns, which halves the stacks and so doubles the work-groups that
+// fit per CU.
+using XyLds = XyLdsT<uint32_t>;
+using XyLdsN = XyLdsT<uint16_t>;
 
 // ---------------------------------------------------------------------------
 // z pass (step 4): tile T = y * ntx + x0 / 64 of a map with nz <= 128, by the
@@ -329,12 +335,15 @@ __device__ __forceinline__ void z_tile(int32_t* d2, int32_t* site, int nx, int n
 // ---------------------------------------------------------------------------
 // xy pass (steps 2-3): tile T = z * ntx + x0 / 64 of a map with ny <= 256,
 // from the map's row records; 512 threads.  Writes the 2D site x' | y' << 16
-// of every voxel of the tile (0xFFFFFFFF if the slice is empty).
+// of every voxel of the tile (0xFFFFFFFF if the slice is empty).  Ent =
+// uint16_t needs nx <= 256.
 // ---------------------------------------------------------------------------
+template <typename Ent>
 __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restrict__ out, int nx, int ny,
-                                        int ntx, int T, XyLds& L)
+                                        int ntx, int T, XyLdsT<Ent>& L)
 {
-    uint32_t* stk = L.stk;
+    constexpr bool NARROW = sizeof(Ent) == 2;
+    Ent* stk = L.stk;
     uint64_t* rw = L.rw;
     int16_t* rl = L.rl;
     int16_t* rr = L.rr;
@@ -382,18 +391,38 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
             return;
         }
     }
+    const uint64_t lmask = col == 63 ? ~0ull : ((2ull << col) - 1ull);   // columns <= xc
+    const uint64_t hmask = ~0ull << col;                                   // columns >= xc
+    // an entry's row y', its K = (x - x')^2 + y'^2, and the entry of (x', y')
+    auto pos = [&](uint32_t e) -> int { return NARROW ? (int)(e & 0xFFu) : (int)(e >> 16); };
     auto key = [&](uint32_t e) {
-        const int d = xc - (int)(e & 0xFFFFu), p = (int)(e >> 16);
+        const int d = NARROW ? (int)(e >> 8) : xc - (int)(e & 0xFFFFu), p = pos(e);
         return mul24(d, d) + mul24(p, p);
     };
-    uint32_t* scol = stk + col;
+    auto make = [&](int xp, int yy) -> Ent {
+        return NARROW ? (Ent)((uint32_t)yy | ((uint32_t)abs(xc - xp) << 8))
+                      : (Ent)((uint32_t)xp | ((uint32_t)yy << 16));
+    };
+    // the site word x' | y' << 16 of an entry.  A narrow entry keeps |x - x'|
+    // only: x' lies left of x exactly when the nearest occupied column at or
+    // left of x in row y' is at that distance (step 1 gives ties to the left)
+    auto site_word = [&](uint32_t e) -> uint32_t {
+        if (!NARROW) return e;
+        const int yq = (int)(e & 0xFFu), a = (int)(e >> 8);
+        int xs = xc;
+        if (a) {
+            const uint64_t lm = rw[yq] & lmask;
+            const int xl = lm ? x0 + 63 - __clzll(lm) : rl[yq];
+            xs = xl >= 0 && xl == xc - a ? xc - a : xc + a;   // xl = -1: none on the left
+        }
+        return (uint32_t)xs | ((uint32_t)yq << 16);
+    };
+    Ent* scol = stk + col;
     auto E = [&](int b, int i) -> uint32_t { return scol[(b * 32 + i) * 64]; };
 
     // ---- band envelope over the band's non-empty rows (wave-uniform loop)
     {
-        const uint64_t lmask = col == 63 ? ~0ull : ((2ull << col) - 1ull);   // columns <= xc
-        const uint64_t hmask = ~0ull << col;                                   // columns >= xc
-        uint32_t* st = scol + band * 32 * 64;
+        Ent* st = scol + band * 32 * 64;
         int top = 0, pa = 0, ka = 0, pb = 0, kb = 0;
         uint32_t bits = __builtin_amdgcn_readfirstlane(rmask[band]);
         while (bits) {
@@ -413,10 +442,10 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
                 pb = pa;
                 kb = ka;
                 const uint32_t e = st[max(top - 2, 0) * 64];
-                pa = (int)(e >> 16);
+                pa = pos(e);
                 ka = key(e);
             }
-            st[top * 64] = (uint32_t)xp | ((uint32_t)yy << 16);
+            st[top * 64] = make(xp, yy);
             ++top;
             pa = pb;
             ka = kb;
@@ -458,19 +487,19 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
             return E(x, LO[x * 64]);
         };
         uint32_t e = E(lastL, hiL - 1);
-        int pt = (int)(e >> 16), kt = key(e);
+        int pt = pos(e), kt = key(e);
         int ps = 0, ks = 0;
         if (cntL >= 2) {
             e = secondL();
-            ps = (int)(e >> 16);
+            ps = pos(e);
             ks = key(e);
         }
         e = E(firstR, loR);
-        int pc = (int)(e >> 16), kc = key(e);
+        int pc = pos(e), kc = key(e);
         int pd = 0, kd = 0;
         if (cntR >= 2) {
             e = secondR();
-            pd = (int)(e >> 16);
+            pd = pos(e);
             kd = key(e);
         }
         for (;;) {
@@ -488,7 +517,7 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
                 kt = ks;
                 if (cntL >= 2) {
                     e = secondL();
-                    ps = (int)(e >> 16);
+                    ps = pos(e);
                     ks = key(e);
                 }
                 continue;
@@ -507,7 +536,7 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
                 kc = kd;
                 if (cntR >= 2) {
                     e = secondR();
-                    pd = (int)(e >> 16);
+                    pd = pos(e);
                     kd = key(e);
                 }
                 continue;
@@ -543,7 +572,7 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 32; ++i)
-            if (i < mcnt) scol[(cum[band] + i) * 64] = ev[i];
+            if (i < mcnt) scol[(cum[band] + i) * 64] = (Ent)ev[i];
         __syncthreads();
     }
 
@@ -555,30 +584,34 @@ __device__ __forceinline__ void xy_tile(const RowRecords& rec, uint32_t* __restr
     while (a < bb) {
         const int mid = (a + bb) >> 1;
         const uint32_t e0 = at(mid), e1 = at(mid + 1);
-        if (key(e1) - 2 * mul24(y0, (int)(e1 >> 16)) < key(e0) - 2 * mul24(y0, (int)(e0 >> 16))) a = mid + 1;
+        if (key(e1) - 2 * mul24(y0, pos(e1)) < key(e0) - 2 * mul24(y0, pos(e0))) a = mid + 1;
         else bb = mid;
     }
     int j = a;
     uint32_t et = at(j);
-    int pt = (int)(et >> 16), kt = key(et);
+    int pt = pos(et), kt = key(et);
     uint32_t en = at(min(j + 1, n - 1));
-    int pn = (int)(en >> 16), kn = key(en);
+    int pn = pos(en), kn = key(en);
     int dp2 = 2 * (pn - pt);
     int g = j + 1 < n ? mul24(y0, dp2) - (kn - kt) : -1;
     uint32_t* o = orow + (size_t)y0 * nx;
+    uint32_t sw = site_word(et);
     for (int yy = y0; yy < y1; ++yy) {
-        while (g > 0) {
-            ++j;
-            et = en;
-            pt = pn;
-            kt = kn;
-            en = at(min(j + 1, n - 1));
-            pn = (int)(en >> 16);
-            kn = key(en);
-            dp2 = 2 * (pn - pt);
-            g = j + 1 < n ? mul24(yy, dp2) - (kn - kt) : -1;
+        if (g > 0) {
+            do {
+                ++j;
+                et = en;
+                pt = pn;
+                kt = kn;
+                en = at(min(j + 1, n - 1));
+                pn = pos(en);
+                kn = key(en);
+                dp2 = 2 * (pn - pt);
+                g = j + 1 < n ? mul24(yy, dp2) - (kn - kt) : -1;
+            } while (g > 0);
+            sw = site_word(et);
         }
-        if (live) o[col] = et;
+        if (live) o[col] = sw;
         o += nx;
         g += dp2;
     }

@@ -20,6 +20,31 @@ def assert_same(occ, oracle_lib, tag):
     assert bad_d == 0 and bad_s == 0, f"{tag}: {bad_d} d2 and {bad_s} site mismatches"
 
 
+def assert_same_many(occ, oracle_lib, tag, min_tiles=1100):
+    """occ as enough separate maps of one edt_compute_many launch that the
+    launch has more than min_tiles xy tiles of 64 columns (past what two
+    work-groups per CU hold, where the xy tiles of maps up to 256 columns
+    switch to 16-bit stack entries); every copy against the oracle."""
+    import torch
+    from paper_2407_02363_amd import edt
+    from tests.gpu_util import dev, grid_of
+    nz, ny, nx = occ.shape
+    k = min(edt.BATCH_MAX, min_tiles // (nz * ((nx + 63) // 64)) + 1)
+    say(f"[edt parity] {tag} shape={occ.shape} as {k} maps of one launch")
+    g = grid_of(occ.shape)
+    flat = torch.from_numpy(np.ascontiguousarray(occ, np.uint8).ravel()).to(dev())
+    occs = [flat.clone() for _ in range(k)]
+    d2s = [torch.full((occ.size,), -7, dtype=torch.int32, device=dev()) for _ in range(k)]
+    sites = [torch.full((occ.size,), -7, dtype=torch.int32, device=dev()) for _ in range(k)]
+    edt.edt_compute_many(edt.batch_maps([g] * k, occs, d2s, sites))
+    torch.cuda.synchronize()
+    rd2, rsite = oracle_lib.edt(occ)
+    for i in range(k):
+        bad_d = int((d2s[i].cpu().numpy().reshape(occ.shape) != rd2).sum())
+        bad_s = int((sites[i].cpu().numpy().reshape(occ.shape) != rsite).sum())
+        assert bad_d == 0 and bad_s == 0, f"{tag} copy {i}: {bad_d} d2 and {bad_s} site mismatches"
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_boxes_64cubed(oracle_lib, seed):
     assert_same(inputs.boxes_grid(64, seed=seed), oracle_lib, f"boxes64 seed{seed}")
@@ -327,3 +352,39 @@ def test_lean_tiles_sparse_slices_and_rows(oracle_lib, shape):
             occ[z, y, g.integers(0, nx, 2)] = 1
     assert_same(occ, oracle_lib, "few rows")
     assert_same(inputs.random_grid(shape, 0.3, nz + ny + nx), oracle_lib, "dense")
+    assert_same_many(occ, oracle_lib, "few rows")
+    assert_same_many(inputs.random_grid(shape, 0.3, nz + ny + nx), oracle_lib, "dense")
+
+
+@pytest.mark.parametrize("nx", [256, 200, 300])
+def test_lean_xy_equidistant_columns(oracle_lib, nx):
+    """Rows whose two nearest occupied columns are equally far from many
+    columns (pairs c - a, c + a, some straddling a 64-column tile boundary,
+    some with the left one outside the tile): the smaller column must win, also
+    where the xy stacks keep only |x - x'| (maps of at most 256 columns) and the
+    side is recovered from the row; and rows with one occupied column, whose
+    left side is empty."""
+    nz, ny = 6, 96
+    g = np.random.Generator(np.random.PCG64(nx))
+    occ = np.zeros((nz, ny, nx), np.uint8)
+    for z in range(nz):
+        for y in range(ny):
+            if y % 14 == 3:
+                continue   # empty rows between
+            if y % 14 == 10:
+                # one occupied column, at an odd position p: column (p - 1) / 2
+                # is p - x = x + 1 away with nothing on its left
+                occ[z, y, 2 * ((y * 3 + z) % ((nx - 1) // 2)) + 1] = 1
+                continue
+            a = 1 + (y * 5 + z) % 40
+            c = int(g.integers(a, nx - a))
+            if y % 5 == 0:
+                c = 64 * int(g.integers(1, max(2, nx // 64))) + (y % 3) - 1   # around a tile seam
+                c = min(max(c, a), nx - 1 - a)
+            occ[z, y, c - a] = 1
+            occ[z, y, c + a] = 1
+            if y % 4 == 1:
+                occ[z, y, min(nx - 1, c + a + 70)] = 1   # a farther one, another tile
+    say(f"[edt] equidistant columns nx={nx}")
+    assert_same(occ, oracle_lib, f"equidistant nx={nx}")
+    assert_same_many(occ, oracle_lib, f"equidistant nx={nx}")
