@@ -15,7 +15,9 @@ Printed as one JSON line:
                "cycle_variants".
   latency      p50 / p99 of the per-cycle latency over >= 1000 cycles, host
                clock from enqueue to the sphere results landing in host
-               memory, plain per-map launches and graph-replayed cycles.
+               memory, plain per-map launches and graph-replayed cycles
+               (three graphs on two streams, and one graph of the cycle
+               with both maps in one launch per pass).
   roofline     the exact transform of one map (its kernels back to back):
                the compulsory 9 bytes per voxel over its average duration
                (HIP events on its own stream) against 8 TB/s; each kernel's
@@ -771,13 +773,13 @@ def main():
     host_env = torch.empty(cyc.out_env.shape, dtype=torch.int32, pin_memory=True)
     host_self = torch.empty(cyc.out_self.shape, dtype=torch.int32, pin_memory=True)
 
-    def latency_run(fn, n):
+    def latency_run(fn, n, c=cyc):
         lat = []
         for k in range(n):
             t = time.perf_counter()
             fn(k)
-            host_env.copy_(cyc.out_env, non_blocking=True)
-            host_self.copy_(cyc.out_self, non_blocking=True)
+            host_env.copy_(c.out_env, non_blocking=True)
+            host_self.copy_(c.out_self, non_blocking=True)
             st.synchronize()
             lat.append(1e3 * (time.perf_counter() - t))
         return lat
@@ -790,6 +792,15 @@ def main():
         lat_graph = latency_run(cyc.replay_split, args.latency_cycles)
         latency["graph"] = {"p50_ms": pct(lat_graph, 50), "p99_ms": pct(lat_graph, 99),
                             "cycles": len(lat_graph), "schedule": "split_graphs"}
+        # both maps in one launch per pass, one graph per cycle
+        cm = ControlCycle(ci, dev, edt_mode="many")
+        gm = cm.capture_graphs(args.graphs)
+        for k in range(args.warmup):
+            gm[k % len(gm)].replay()
+        lat_many = latency_run(lambda k: gm[k % len(gm)].replay(), args.latency_cycles, cm)
+        latency["graph_one_launch_per_pass"] = {"p50_ms": pct(lat_many, 50), "p99_ms": pct(lat_many, 99),
+                                                "cycles": len(lat_many), "schedule": "many_one_stream graph"}
+        del gm, cm
 
     # ---- the host -> device upload of one frame, which a live sensor adds to
     # every cycle (Alg. 2 inserts a new cloud each cycle): pinned host buffer

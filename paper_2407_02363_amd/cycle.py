@@ -37,8 +37,13 @@ class ControlCycle:
         self.self_mask = int(self_mask)
         n = ci.grid.n
         d = self.dev
-        self.occ_self = torch.zeros(n, dtype=torch.uint8, device=d)
-        self.occ_env = torch.zeros(n, dtype=torch.uint8, device=d)
+        # both occupancy maps in one buffer, so that one clear over a grid of
+        # twice the depth zeroes both
+        self.occ_both = torch.zeros(2 * n, dtype=torch.uint8, device=d)
+        self.occ_env = self.occ_both[:n]
+        self.occ_self = self.occ_both[n:]
+        g = ci.grid
+        self.grid2 = inputs.Grid(g.nx, g.ny, 2 * g.nz, g.origin, g.voxel)
         self.d2_self = torch.empty(n, dtype=torch.int32, device=d)
         self.site_self = torch.empty(n, dtype=torch.int32, device=d)
         self.d2_env = torch.empty(n, dtype=torch.int32, device=d)
@@ -85,8 +90,12 @@ class ControlCycle:
         g = self.grid
         f = k % self.n_frames
         s = k % self.n_states
-        edt.edt_clear(g, self.occ_self, stream)
-        edt.edt_clear(g, self.occ_env, stream)
+        joint = self.edt_mode != "per_map"   # one clear and one query launch for both maps
+        if joint:
+            edt.edt_clear(self.grid2, self.occ_both, stream)
+        else:
+            edt.edt_clear(g, self.occ_self, stream)
+            edt.edt_clear(g, self.occ_env, stream)
         edt.edt_insert_links(g, self.occ_self, self.link_pts, self.link_off, self.poses[s],
                              self.self_mask, stream)
         edt.edt_insert_points(g, self.occ_env, self.frames[f], self.T, exclude=self.occ_self,
@@ -98,10 +107,15 @@ class ControlCycle:
         else:
             edt.edt_compute(g, self.occ_env, self.d2_env, self.site_env, stream=stream)
             edt.edt_compute(g, self.occ_self, self.d2_self, self.site_self, stream=stream)
-        edt.edt_query_spheres(g, self.d2_env, self.site_env, self.centres[s], self.radii,
-                              self.out_env, stream)
-        edt.edt_query_spheres(g, self.d2_self, self.site_self, self.centres[s], self.radii,
-                              self.out_self, stream)
+        if joint:
+            c = self.centres[s]
+            edt.edt_query_spheres_many(self.maps, [c, c], [self.radii, self.radii],
+                                       [self.out_env, self.out_self], stream)
+        else:
+            edt.edt_query_spheres(g, self.d2_env, self.site_env, self.centres[s], self.radii,
+                                  self.out_env, stream)
+            edt.edt_query_spheres(g, self.d2_self, self.site_self, self.centres[s], self.radii,
+                                  self.out_self, stream)
 
     def _run_two_streams(self, k: int, stream=None):
         g = self.grid
